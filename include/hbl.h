@@ -1,0 +1,165 @@
+/*
+ * hbl.h -- C ABI of libhbl, hybrid beamline tracking on one AMD MI355X.
+ *
+ * The library pushes an electron bunch in 6-D phase space through a beamline
+ * of conventional elements (drift, thick quadrupole, sector bend, thin plasma
+ * lens) and plasma-accelerator stages, each stage taken either by a fine-step
+ * reference integrator or by a small neural-network surrogate, as in the
+ * hybrid conventional + surrogate beamline of Sandberg et al., "Synthesizing
+ * Particle-in-Cell Simulations Through Learning and GPU Computing for Hybrid
+ * Particle Accelerator Beamlines", PASC '24 (§2).  Every element is a
+ * per-particle map of R^6 with no collective effects (§1), so every call is
+ * data parallel over particles.
+ *
+ * CONVENTIONS
+ *  - Bunch: `z` is a DEVICE pointer to six FP64 rows of `n` particles, row j at
+ *    z + j*ld: x, y, t, px, py, pt (row order 0..5) relative to the reference
+ *    particle.  x, y, t in metres (t = c*(t_particle - t_ref), positive =
+ *    later), px = p_x/p_ref, py = p_y/p_ref, pt = -(E - E_ref)/(p_ref c).
+ *    `z` must be 16-byte aligned and `ld` even, ld >= n.  The caller owns the
+ *    memory (e.g. a torch tensor of shape (6, ld)); the library never frees
+ *    it.  n == 0 is a valid no-op.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls
+ *    marked ASYNC only enqueue work on it; calls marked SYNC wait for it.
+ *    Particle data never leaves the device (§2, §4.3).
+ *  - Errors: every call returns an hbl_status; arguments are validated before
+ *    any GPU work is enqueued, and a rejected call has no effect.
+ *    hbl_last_error() gives a message for the calling thread's last failure.
+ *    A device fault in enqueued work surfaces at the next SYNC call.  No C++
+ *    exception crosses this interface.
+ *  - Handles (lattice, surrogate) own small device buffers on the device that
+ *    was current when they were created; use them with that device current.
+ *    A handle must not be used by two threads at once.
+ */
+#ifndef HBL_H
+#define HBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hbl_status;
+#define HBL_OK 0
+#define HBL_EINVAL (-1)     /* bad argument; nothing was enqueued */
+#define HBL_EHIP (-2)       /* HIP runtime error */
+#define HBL_ENOMEM (-3)     /* device or host allocation failed */
+#define HBL_ENONFINITE (-4) /* a reduction met NaN or Inf particle data */
+#define HBL_ESTATE (-5)     /* handle used in a state that does not allow it */
+#define HBL_EIO (-6)        /* file I/O or format error */
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* hbl_last_error(void);
+/* Library version string. */
+const char* hbl_version(void);
+
+/* Reference particle (host POD).  gamma is its Lorentz factor; s the path
+ * length along the beamline [m] (§1: s is the independent variable). */
+typedef struct hbl_ref {
+    double mass_MeV; /* rest energy, 0.51099895 for electrons */
+    double gamma;
+    double s;
+} hbl_ref;
+
+/* Element kinds. */
+#define HBL_DRIFT 1
+#define HBL_QUAD 2
+#define HBL_SBEND 3
+#define HBL_THIN_LENS 4
+#define HBL_STAGE 5
+
+/* One beamline element (host POD).  Fields not used by a kind are ignored.
+ *  DRIFT     L
+ *  QUAD      L, k [m^-2] (k > 0 focuses x, defocuses y)
+ *  SBEND     L, angle [rad] (sector bend, hard edge, no edge focusing)
+ *  THIN_LENS f [m] (plasma lens: px -= x/f, py -= y/f; §4, Fig. 1)
+ *  STAGE     L, n0_m3 [m^-3], dE_MeV, nsub (plasma stage, §4) */
+typedef struct hbl_element {
+    int32_t kind;
+    int32_t nsub;
+    double L;
+    double k;
+    double angle;
+    double f;
+    double n0_m3;
+    double dE_MeV;
+} hbl_element;
+
+typedef void* hbl_stream;
+
+/* ---------------------------------------------------------------- bunch */
+
+/* ASYNC.  Fill particles [0, n) with independent Gaussians: coordinate j of
+ * particle i is mean[j] + sigma[j]*N(0,1), drawn by Philox4x32-10 keyed by
+ * `seed` with counter (i0 + i, pair, ...) and the Box-Muller transform; pairs
+ * (x,y), (t,px), (py,pt).  The same (seed, i0 + i) always gives the same
+ * particle, so a bunch can be filled in pieces.  Stands in for the Gaussian
+ * bunches of the paper's simulations (§4.1).  mean, sigma: host arrays of 6. */
+hbl_status hbl_bunch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
+                                   const double mean[6], const double sigma[6], int64_t i0,
+                                   hbl_stream stream);
+
+/* ---------------------------------------------------------------- lattice */
+
+typedef struct hbl_lattice hbl_lattice;
+
+/* Compile a sequence of linear elements (DRIFT, QUAD, SBEND, THIN_LENS; no
+ * STAGE) for a reference particle of Lorentz factor ref->gamma into a device
+ * coefficient table (first-order transfer maps of each element, §1).
+ * Synchronous (uploads the table).  *out receives the handle. */
+hbl_status hbl_lattice_create(const hbl_element* elems, int32_t n_elem, const hbl_ref* ref,
+                              hbl_lattice** out);
+hbl_status hbl_lattice_destroy(hbl_lattice* lat);
+/* Total length [m] and element count of a compiled lattice. */
+hbl_status hbl_lattice_info(const hbl_lattice* lat, double* length, int32_t* n_elem);
+
+#define HBL_FUSED 0u   /* one kernel; each particle stays in registers through all elements */
+#define HBL_UNFUSED 1u /* one kernel per element (comparator) */
+
+/* ASYNC.  Push the bunch through the lattice in place.  ref->gamma must equal
+ * the gamma the lattice was compiled for; ref->s advances by its length.
+ * Fused and unfused paths give bitwise identical results. */
+hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice* lat,
+                            hbl_ref* ref, uint32_t flags, hbl_stream stream);
+
+/* ---------------------------------------------------------------- stage */
+
+/* ASYNC.  Fine-step reference map of one plasma-accelerator stage (the LPA
+ * stage of §4, a nonlinear per-particle map; the paper models it with PIC).
+ * Model: linear ion-channel focusing du/ds = -(k_p^2/2) x on u = p_x/(m c),
+ * drift dx/ds = u/gamma_i(s) with the particle's own gamma_i(s) =
+ * gamma_ref(s) + dgamma_i, gamma_ref ramping linearly by dE over L, nsub
+ * kick-drift-kick substeps; every particle gains the same energy.  ref->gamma
+ * and ref->s advance.  If `record` is not NULL (rows at record + j*record_ld,
+ * same alignment rules) it receives a copy of the input bunch, so the call
+ * emits (input, output) training pairs (§3). */
+hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* stage,
+                           hbl_ref* ref, double* record, int64_t record_ld, hbl_stream stream);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+/* SYNC.  Beam moments (§4): mean6[j] = <z_j>; cov21 = centred population
+ * covariance <(z_j - <z_j>)(z_k - <z_k>)>, upper triangle row-major
+ * (00,01,..,05,11,..,55).  Unweighted.  Compensated FP64 (double-double)
+ * reduction in a fixed order: bitwise reproducible.  HBL_ENONFINITE if the
+ * bunch holds NaN/Inf.  n >= 1. */
+hbl_status hbl_moments(const double* z, int64_t n, int64_t ld, double mean6[6], double cov21[21],
+                       hbl_stream stream);
+/* ASYNC variant: writes the 27 doubles (mean6 then cov21) to DEVICE memory
+ * out27 (8-byte aligned). */
+hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out27,
+                             hbl_stream stream);
+/* Host only.  Geometric RMS emittances of (x,px), (y,py), (t,pt),
+ * eps = sqrt(<dx^2><dpx^2> - <dx dpx>^2) (§4). */
+hbl_status hbl_emittances(const double cov21[21], double eps3[3]);
+/* SYNC.  Error metrics of a test bunch zs against a reference bunch zf (same
+ * n, ld): rms6[j] = sqrt(<(s_j - f_j)^2>)/sigma_f,j; centroid6[j] =
+ * (<s_j> - <f_j>)/sigma_f,j; eps_rel3[p] = eps_s,p/eps_f,p - 1. */
+hbl_status hbl_compare(const double* zs, const double* zf, int64_t n, int64_t ld, double rms6[6],
+                       double centroid6[6], double eps_rel3[3], hbl_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HBL_H */

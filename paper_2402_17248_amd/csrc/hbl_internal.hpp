@@ -1,0 +1,67 @@
+// Internal declarations shared by the libhbl translation units (not part of
+// the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace hbl {
+
+// ----------------------------------------------------------------- errors
+void set_error(int code, const char* fmt, ...);
+void clear_error();
+
+// ------------------------------------------------------ compiled elements
+// First-order transfer map coefficients of one linear element, computed on
+// the host in FP64 for the reference particle the lattice was compiled for.
+//  DRIFT : c[0] = L, c[1] = L/(beta gamma)^2
+//  QUAD  : c[0..3] = x-plane m11 m12 m21 m22, c[4..7] = y-plane, c[8] = L/(beta gamma)^2
+//  SBEND : c[0] m11, c[1] m12, c[2] m16, c[3] m21, c[4] m22, c[5] m26,
+//          c[6] m51, c[7] m52, c[8] m56, c[9] L (vertical drift)
+//  LENS  : c[0] = -1/f
+constexpr int kCoef = 12;
+enum ElemKind : int32_t { kDrift = 1, kQuad = 2, kSbend = 3, kLens = 4 };
+
+struct ElemCoef {
+    double c[kCoef];
+};
+
+// ----------------------------------------------------------- stage params
+struct StageParams {
+    double bg_in;          // (beta gamma)_ref at entry
+    double h;              // substep length
+    double hk2;            // h^2 kappa (merged full kick on v = h u)
+    double half_hk2;       // h^2 kappa / 2
+    double inv_h_bgout;    // 1/(h (beta gamma)_out)
+    double pt_scale;       // (beta gamma)_in / (beta gamma)_out
+    double r56;            // first-order flight-time coefficient
+    int32_t nsub;
+    int32_t newton;        // Newton steps per substep (0 = divide every substep)
+};
+
+// ------------------------------------------------------------- launchers
+// All launchers validate nothing (the ABI layer does) and return the HIP
+// launch status.
+hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
+                                const double* mean, const double* sigma, int64_t i0,
+                                hipStream_t s);
+hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const int32_t* kinds,
+                                const double* coef, int32_t n_elem, hipStream_t s);
+hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind,
+                                  const ElemCoef& c, hipStream_t s);
+hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
+                        const StageParams& p, const double* gmid, hipStream_t s);
+
+// Reductions.  `ws` is device scratch of at least reduce_ws_bytes(n) bytes.
+size_t reduce_ws_bytes(int64_t n);
+hipError_t launch_moments(const double* z, int64_t n, int64_t ld, double* ws, double* out27,
+                          hipStream_t s);
+hipError_t launch_diff2(const double* zs, const double* zf, int64_t n, int64_t ld, double* ws,
+                        double* out6, hipStream_t s);
+
+// Per-device library workspace (grow-only, freed at exit).
+double* workspace(size_t bytes);
+
+}  // namespace hbl

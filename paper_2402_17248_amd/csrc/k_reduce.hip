@@ -1,0 +1,246 @@
+// Diagnostics reductions for gfx950: beam moments (means and centred
+// covariance, §4) and the paired squared-difference sums used by the error
+// metrics.  FP64 throughout.
+//
+// Scheme (fixed order, hence bitwise reproducible run to run):
+//  1. each thread sums its particles (grid-stride, at most ~100 per thread)
+//     in plain FP64 into NV accumulators, coordinates shifted by particle 0
+//     so that the second moments do not cancel against the mean;
+//  2. the 64 lanes of a wavefront merge their sums as double-double pairs
+//     (error-free TwoSum) through cross-lane shuffles, the waves of a block
+//     through LDS, and each block writes NV double-double partials;
+//  3. one block merges the partials in double-double and forms
+//     mean = shift + S/n and cov = (P - S_j S_k / n) / n.
+// Compiled with -ffp-contract=off: the TwoSum sequences must not be fused.
+#include "hbl_internal.hpp"
+
+namespace hbl {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxBlocks = 1024;
+
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD two_sum(double a, double b) {
+    const double s = a + b;
+    const double bp = s - a;
+    const double e = (a - (s - bp)) + (b - bp);
+    return {s, e};
+}
+
+__device__ __forceinline__ DD quick_two_sum(double a, double b) {
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+    DD s = two_sum(a.hi, b.hi);
+    const DD t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ DD dd_mul(DD a, DD b) {
+    const double p = a.hi * b.hi;
+    double e = fma(a.hi, b.hi, -p);
+    e = fma(a.hi, b.lo, e);
+    e = fma(a.lo, b.hi, e);
+    return quick_two_sum(p, e);
+}
+
+__device__ __forceinline__ DD dd_div_d(DD a, double b) {
+    const double q1 = a.hi / b;
+    const double ph = q1 * b;
+    const double pl = fma(q1, b, -ph);
+    DD s = two_sum(a.hi, -ph);
+    s.lo -= pl;
+    s.lo += a.lo;
+    const double q2 = (s.hi + s.lo) / b;
+    return quick_two_sum(q1, q2);
+}
+
+__device__ __forceinline__ DD dd_neg(DD a) { return {-a.hi, -a.lo}; }
+
+// Merge NV double-double values across the block; lanes 0..NV-1 of wave 0
+// hold the block totals on return (others undefined).
+template <int NV>
+__device__ void block_reduce_dd(DD (&v)[NV], DD* lds) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            DD o;
+            o.hi = __shfl_xor(v[q].hi, off, 64);
+            o.lo = __shfl_xor(v[q].lo, off, 64);
+            v[q] = dd_add(v[q], o);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[wave * NV + q] = v[q];
+    }
+    __syncthreads();
+}
+
+// Per-particle contributions.
+// Shift = particle 0 (read on the device; uniform across the grid).
+struct MomentsOp {
+    static constexpr int NV = 27;
+    const double* z;
+    int64_t ld;
+    double sh[6];
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) sh[j] = z[j * ld];
+    }
+    __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
+        double d[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) d[j] = z[j * ld + i] - sh[j];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[j] += d[j];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+#pragma unroll
+            for (int k = j; k < 6; ++k) {
+                const int q = 6 + j * 6 - j * (j - 1) / 2 + (k - j);
+                acc[q] = fma(d[j], d[k], acc[q]);
+            }
+    }
+};
+
+struct Diff2Op {
+    static constexpr int NV = 6;
+    const double* zs;
+    const double* zf;
+    int64_t ld;
+    __device__ __forceinline__ void init() {}
+    __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double d = zs[j * ld + i] - zf[j * ld + i];
+            acc[j] = fma(d, d, acc[j]);
+        }
+    }
+};
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_partials(Op op, int64_t n, DD* __restrict__ part) {
+    constexpr int NV = Op::NV;
+    op.init();
+    __shared__ DD lds[kWaves * NV];
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) op.add(i, acc);
+    DD v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = DD{acc[q], 0.0};
+    block_reduce_dd<NV>(v, lds);
+    if (threadIdx.x < NV) {
+        const int q = threadIdx.x;
+        DD s = lds[q];
+        for (int w = 1; w < kWaves; ++w) s = dd_add(s, lds[w * NV + q]);
+        part[(int64_t)blockIdx.x * NV + q] = s;
+    }
+}
+
+// One block: total of nb partials per value, fixed order.
+template <int NV>
+__device__ void merge_partials(const DD* __restrict__ part, int nb, DD* tot) {
+    __shared__ DD red[kBlock];
+    for (int q = 0; q < NV; ++q) {
+        DD s{0.0, 0.0};
+        for (int b = threadIdx.x; b < nb; b += kBlock) s = dd_add(s, part[(int64_t)b * NV + q]);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w >= 1; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] = dd_add(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[q] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_moments_final(const DD* __restrict__ part, int nb,
+                                                          const double* __restrict__ z,
+                                                          int64_t ld, int64_t n,
+                                                          double* __restrict__ out) {
+    __shared__ DD tot[27];
+    merge_partials<27>(part, nb, tot);
+    if (threadIdx.x == 0) {
+        const double nd = (double)n;
+        for (int j = 0; j < 6; ++j) {
+            // mean = shift + S/n, the shift being particle 0
+            const DD m = dd_div_d(tot[j], nd);
+            const DD mean = dd_add(DD{z[(int64_t)j * ld], 0.0}, m);
+            out[j] = mean.hi + mean.lo;
+        }
+        int q = 6;
+        for (int j = 0; j < 6; ++j)
+            for (int k = j; k < 6; ++k, ++q) {
+                DD t = dd_div_d(dd_mul(tot[j], tot[k]), nd);
+                DD u = dd_add(tot[q], dd_neg(t));
+                DD c = dd_div_d(u, nd);
+                out[q] = c.hi + c.lo;
+            }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_diff2_final(const DD* __restrict__ part, int nb,
+                                                        double* __restrict__ out) {
+    __shared__ DD tot[6];
+    merge_partials<6>(part, nb, tot);
+    if (threadIdx.x < 6) out[threadIdx.x] = tot[threadIdx.x].hi + tot[threadIdx.x].lo;
+}
+
+int reduce_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > kMaxBlocks) g = kMaxBlocks;
+    return (int)g;
+}
+
+}  // namespace
+
+size_t reduce_ws_bytes(int64_t n) {
+    return (size_t)reduce_grid(n) * 27 * sizeof(DD);
+}
+
+hipError_t launch_moments(const double* z, int64_t n, int64_t ld, double* ws, double* out27,
+                          hipStream_t s) {
+    const int nb = reduce_grid(n);
+    MomentsOp op;
+    op.z = z;
+    op.ld = ld;
+    for (int j = 0; j < 6; ++j) op.sh[j] = 0.0;  // loaded on the device by init()
+    DD* part = reinterpret_cast<DD*>(ws);
+    hipLaunchKernelGGL(k_partials<MomentsOp>, dim3(nb), dim3(kBlock), 0, s, op, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, s, part, nb, z, ld, n, out27);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff2(const double* zs, const double* zf, int64_t n, int64_t ld, double* ws,
+                        double* out6, hipStream_t s) {
+    const int nb = reduce_grid(n);
+    Diff2Op op{zs, zf, ld};
+    DD* part = reinterpret_cast<DD*>(ws);
+    hipLaunchKernelGGL(k_partials<Diff2Op>, dim3(nb), dim3(kBlock), 0, s, op, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diff2_final, dim3(1), dim3(kBlock), 0, s, part, nb, out6);
+    return hipGetLastError();
+}
+
+}  // namespace hbl

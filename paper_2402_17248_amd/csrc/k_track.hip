@@ -1,0 +1,345 @@
+// Tracking kernels for gfx950: Gaussian bunch fill, fused and per-element
+// lattice push, fine-step plasma stage.  All FP64.  Bunch rows are SoA
+// (x, y, t, px, py, pt at z + j*ld): every load and store below is a
+// unit-stride access across the lanes of a wavefront.
+//
+// Compiled with -ffp-contract=off: every fused multiply-add is written out
+// as fma(), so the fused and per-element lattice paths execute the same
+// operations in the same order and agree bitwise.
+#include "hbl_internal.hpp"
+
+namespace hbl {
+namespace {
+
+constexpr int kBlock = 256;
+
+// --------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit products, key advanced by the Weyl constants each round.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+struct FillArgs {
+    double mean[6];
+    double sigma[6];
+};
+
+// One thread per particle.  Pair q of particle g: counter (g_lo, g_hi, q,
+// "GAUS"), two 53-bit uniforms u1 in (0,1], u2 in [0,1), Box-Muller.
+__global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z, int64_t n,
+                                                          int64_t ld, uint32_t key0,
+                                                          uint32_t key1, int64_t i0,
+                                                          FillArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t g = (uint64_t)(i0 + i);
+#pragma unroll
+        for (uint32_t q = 0; q < 3; ++q) {
+            uint32_t c0 = (uint32_t)g, c1 = (uint32_t)(g >> 32), c2 = q, c3 = 0x47415553u;
+            philox4x32_10(c0, c1, c2, c3, key0, key1);
+            const uint64_t ua = ((uint64_t)(c0 >> 5) << 26) | (c1 >> 6);
+            const uint64_t ub = ((uint64_t)(c2 >> 5) << 26) | (c3 >> 6);
+            const double u1 = ((double)ua + 1.0) * 0x1.0p-53;
+            const double u2 = (double)ub * 0x1.0p-53;
+            const double r = sqrt(-2.0 * log(u1));
+            const double ang = 2.0 * M_PI * u2;
+            const double cs = cos(ang), sn = sin(ang);
+            z[(2 * q) * ld + i] = a.mean[2 * q] + a.sigma[2 * q] * (r * cs);
+            z[(2 * q + 1) * ld + i] = a.mean[2 * q + 1] + a.sigma[2 * q + 1] * (r * sn);
+        }
+    }
+}
+
+// --------------------------------------------------------------- lattice
+struct P6 {
+    double x, y, t, px, py, pt;
+};
+
+__device__ __forceinline__ void el_drift(P6& p, const double* c) {
+    p.x = fma(c[0], p.px, p.x);
+    p.y = fma(c[0], p.py, p.y);
+    p.t = fma(c[1], p.pt, p.t);
+}
+
+__device__ __forceinline__ void el_quad(P6& p, const double* c) {
+    const double x = p.x, px = p.px, y = p.y, py = p.py;
+    p.x = fma(c[1], px, c[0] * x);
+    p.px = fma(c[3], px, c[2] * x);
+    p.y = fma(c[5], py, c[4] * y);
+    p.py = fma(c[7], py, c[6] * y);
+    p.t = fma(c[8], p.pt, p.t);
+}
+
+__device__ __forceinline__ void el_sbend(P6& p, const double* c) {
+    const double x = p.x, px = p.px, pt = p.pt;
+    p.x = fma(c[2], pt, fma(c[1], px, c[0] * x));
+    p.px = fma(c[5], pt, fma(c[4], px, c[3] * x));
+    p.y = fma(c[9], p.py, p.y);
+    p.t = fma(c[8], pt, fma(c[7], px, fma(c[6], x, p.t)));
+}
+
+__device__ __forceinline__ void el_lens(P6& p, const double* c) {
+    p.px = fma(c[0], p.x, p.px);
+    p.py = fma(c[0], p.y, p.py);
+}
+
+__device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {
+    p.x = z[i];
+    p.y = z[ld + i];
+    p.t = z[2 * ld + i];
+    p.px = z[3 * ld + i];
+    p.py = z[4 * ld + i];
+    p.pt = z[5 * ld + i];
+}
+
+__device__ __forceinline__ void store6(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
+    z[i] = p.x;
+    z[ld + i] = p.y;
+    z[2 * ld + i] = p.t;
+    z[3 * ld + i] = p.px;
+    z[4 * ld + i] = p.py;
+    z[5 * ld + i] = p.pt;
+}
+
+// Fused lattice: a grid-stride (persistent) loop over tiles of kPer*kBlock
+// particles; each thread keeps kPer particles in registers through the
+// whole element sequence.  The element kind and coefficients are uniform
+// across the wavefront (scalar loads, scalar branch).
+constexpr int kPer = 2;
+
+__global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z, int64_t n,
+                                                          int64_t ld,
+                                                          const int32_t* __restrict__ kinds,
+                                                          const double* __restrict__ coef,
+                                                          int32_t n_elem) {
+    const int64_t tile = (int64_t)kPer * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
+        P6 p[kPer];
+        bool live[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            live[k] = i < n;
+            if (live[k]) load6(z, ld, i, p[k]);
+            else p[k] = P6{0, 0, 0, 0, 0, 0};
+        }
+        for (int32_t e = 0; e < n_elem; ++e) {
+            const double* c = coef + (int64_t)e * kCoef;
+            switch (kinds[e]) {
+                case kDrift:
+#pragma unroll
+                    for (int k = 0; k < kPer; ++k) el_drift(p[k], c);
+                    break;
+                case kQuad:
+#pragma unroll
+                    for (int k = 0; k < kPer; ++k) el_quad(p[k], c);
+                    break;
+                case kSbend:
+#pragma unroll
+                    for (int k = 0; k < kPer; ++k) el_sbend(p[k], c);
+                    break;
+                default:
+#pragma unroll
+                    for (int k = 0; k < kPer; ++k) el_lens(p[k], c);
+                    break;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            if (live[k]) store6(z, ld, i, p[k]);
+        }
+    }
+}
+
+// Per-element comparator: one launch per element, loading and storing only
+// the rows that element reads and writes.
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_lattice_one(double* __restrict__ z, int64_t n,
+                                                        int64_t ld, ElemCoef ec) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        P6 p;
+        if (KIND == kLens) {
+            p.x = z[i];
+            p.y = z[ld + i];
+            p.px = z[3 * ld + i];
+            p.py = z[4 * ld + i];
+            el_lens(p, ec.c);
+            z[3 * ld + i] = p.px;
+            z[4 * ld + i] = p.py;
+        } else {
+            load6(z, ld, i, p);
+            if (KIND == kDrift) {
+                el_drift(p, ec.c);
+                z[i] = p.x;
+                z[ld + i] = p.y;
+                z[2 * ld + i] = p.t;
+            } else if (KIND == kQuad) {
+                el_quad(p, ec.c);
+                z[i] = p.x;
+                z[ld + i] = p.y;
+                z[2 * ld + i] = p.t;
+                z[3 * ld + i] = p.px;
+                z[4 * ld + i] = p.py;
+            } else {
+                el_sbend(p, ec.c);
+                z[i] = p.x;
+                z[ld + i] = p.y;
+                z[2 * ld + i] = p.t;
+                z[3 * ld + i] = p.px;
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- stage
+// One thread per particle, the whole stage in registers.  Variables
+// v = h u (u = p/(m c)) so a kick is v -= h^2 kappa x and a drift is
+// x += v / gamma_i.  Adjacent half kicks are merged.  1/gamma_i(s_n) is
+// refined from the previous substep's reciprocal by NEWTON Newton steps
+// r <- r (2 - a r) (the relative change per substep is small, checked by the
+// host); NEWTON == 0 divides every substep.  gmid[n] = gamma_ref at the
+// middle of substep n (uniform across the wavefront: scalar loads).
+template <int NEWTON>
+__global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_t n, int64_t ld,
+                                                  double* __restrict__ rec, int64_t rld,
+                                                  StageParams sp,
+                                                  const double* __restrict__ gmid) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        P6 p;
+        load6(z, ld, i, p);
+        if (rec) store6(rec, rld, i, p);
+        const double dg = -p.pt * sp.bg_in;
+        const double hb = sp.h * sp.bg_in;
+        double x = p.x, y = p.y;
+        double vx = p.px * hb, vy = p.py * hb;
+        vx = fma(-sp.half_hk2, x, vx);
+        vy = fma(-sp.half_hk2, y, vy);
+        double a = gmid[0] + dg;
+        double r = 1.0 / a;
+        x = fma(vx, r, x);
+        y = fma(vy, r, y);
+        for (int32_t s = 1; s < sp.nsub; ++s) {
+            vx = fma(-sp.hk2, x, vx);
+            vy = fma(-sp.hk2, y, vy);
+            a = gmid[s] + dg;
+            if (NEWTON == 0) {
+                r = 1.0 / a;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NEWTON; ++q) {
+                    const double e = fma(-a, r, 1.0);
+                    r = fma(r, e, r);
+                }
+            }
+            x = fma(vx, r, x);
+            y = fma(vy, r, y);
+        }
+        vx = fma(-sp.half_hk2, x, vx);
+        vy = fma(-sp.half_hk2, y, vy);
+        p.x = x;
+        p.y = y;
+        p.px = vx * sp.inv_h_bgout;
+        p.py = vy * sp.inv_h_bgout;
+        p.t = fma(sp.r56, p.pt, p.t);
+        p.pt = p.pt * sp.pt_scale;
+        store6(z, ld, i, p);
+    }
+}
+
+int grid_for(int64_t n, int64_t per_block, int cap) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
+                                const double* mean, const double* sigma, int64_t i0,
+                                hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    FillArgs a;
+    for (int j = 0; j < 6; ++j) {
+        a.mean[j] = mean[j];
+        a.sigma[j] = sigma[j];
+    }
+    const int grid = grid_for(n, kBlock, 1 << 20);
+    hipLaunchKernelGGL(k_fill_gaussian, dim3(grid), dim3(kBlock), 0, s, z, n, ld,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), i0, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const int32_t* kinds,
+                                const double* coef, int32_t n_elem, hipStream_t s) {
+    if (n == 0 || n_elem == 0) return hipSuccess;
+    // persistent grid: at most 8 blocks per CU of the 256-CU part
+    const int grid = grid_for(n, (int64_t)kPer * kBlock, 2048);
+    hipLaunchKernelGGL(k_lattice_fused, dim3(grid), dim3(kBlock), 0, s, z, n, ld, kinds, coef,
+                       n_elem);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind,
+                                  const ElemCoef& c, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(n, kBlock, 1 << 20);
+    switch (kind) {
+        case kDrift:
+            hipLaunchKernelGGL(k_lattice_one<kDrift>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, c);
+            break;
+        case kQuad:
+            hipLaunchKernelGGL(k_lattice_one<kQuad>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, c);
+            break;
+        case kSbend:
+            hipLaunchKernelGGL(k_lattice_one<kSbend>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, c);
+            break;
+        default:
+            hipLaunchKernelGGL(k_lattice_one<kLens>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, c);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
+                        const StageParams& p, const double* gmid, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(n, kBlock, 1 << 20);
+    switch (p.newton) {
+        case 1:
+            hipLaunchKernelGGL(k_stage<1>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_stage<2>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
+            break;
+        case 3:
+            hipLaunchKernelGGL(k_stage<3>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
+            break;
+        default:
+            hipLaunchKernelGGL(k_stage<0>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hbl

@@ -1,0 +1,205 @@
+"""Thin Python binding of libhbl (argument marshalling only).
+
+Every step of the hot path runs in libhbl's HIP kernels; this module converts
+arguments, owns no computation, and raises :class:`HblError` on any non-zero
+status.  Torch is used for device memory (bunch tensors of shape (6, ld),
+FP64, contiguous) and for the current HIP stream.  If libhbl.so is missing
+the import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libhbl.so")
+
+HBL_OK, HBL_EINVAL, HBL_EHIP, HBL_ENOMEM, HBL_ENONFINITE, HBL_ESTATE, HBL_EIO = 0, -1, -2, -3, -4, -5, -6
+DRIFT, QUAD, SBEND, THIN_LENS, STAGE = 1, 2, 3, 4, 5
+FUSED, UNFUSED = 0, 1
+MEC2_MEV = 0.51099895000
+
+_KIND = {"drift": DRIFT, "quad": QUAD, "sbend": SBEND, "thin_lens": THIN_LENS, "stage": STAGE}
+
+
+class HblError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class Element(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nsub", C.c_int32), ("L", C.c_double), ("k", C.c_double),
+                ("angle", C.c_double), ("f", C.c_double), ("n0_m3", C.c_double), ("dE_MeV", C.c_double)]
+
+
+class Ref(C.Structure):
+    _fields_ = [("mass_MeV", C.c_double), ("gamma", C.c_double), ("s", C.c_double)]
+
+    @staticmethod
+    def from_energy(E_MeV: float, s: float = 0.0) -> "Ref":
+        return Ref(MEC2_MEV, E_MeV / MEC2_MEV, s)
+
+    def copy(self) -> "Ref":
+        return Ref(self.mass_MeV, self.gamma, self.s)
+
+
+def _load():
+    # torch's HIP runtime must be the one libhbl binds to: import torch first,
+    # so that libhbl's libamdhip64.so.7 dependency resolves (by soname) to the
+    # copy torch already loaded, and the process holds a single HIP runtime.
+    import torch  # noqa: F401
+    if not os.path.exists(SO_PATH):
+        raise ImportError(f"libhbl.so not built at {SO_PATH}: run `python -m paper_2402_17248_amd.build` "
+                          "(the HIP library is required; there is no CPU fallback)")
+    L = C.CDLL(SO_PATH)
+    vp, dp, i64, i32, st = C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.c_int32, C.c_int32
+    sigs = {
+        "hbl_last_error": ([], C.c_char_p),
+        "hbl_version": ([], C.c_char_p),
+        "hbl_bunch_fill_gaussian": ([vp, i64, i64, C.c_uint64, dp, dp, i64, vp], st),
+        "hbl_lattice_create": ([C.POINTER(Element), i32, C.POINTER(Ref), C.POINTER(vp)], st),
+        "hbl_lattice_destroy": ([vp], st),
+        "hbl_lattice_info": ([vp, dp, C.POINTER(i32)], st),
+        "hbl_push_lattice": ([vp, i64, i64, vp, C.POINTER(Ref), C.c_uint32, vp], st),
+        "hbl_apply_stage": ([vp, i64, i64, C.POINTER(Element), C.POINTER(Ref), vp, i64, vp], st),
+        "hbl_moments": ([vp, i64, i64, dp, dp, vp], st),
+        "hbl_moments_async": ([vp, i64, i64, vp, vp], st),
+        "hbl_emittances": ([dp, dp], st),
+        "hbl_compare": ([vp, vp, i64, i64, dp, dp, dp, vp], st),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _call(name, *args):
+    rc = getattr(lib, name)(*args)
+    if rc != HBL_OK:
+        raise HblError(rc, name, lib.hbl_last_error().decode())
+    return rc
+
+
+def exported_symbols() -> Sequence[str]:
+    return [n for n in dir(lib) if n.startswith("hbl_")]
+
+
+def version() -> str:
+    return lib.hbl_version().decode()
+
+
+# ------------------------------------------------------------------ helpers
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def new_bunch(n: int, device="cuda"):
+    """Device tensor (6, ld) FP64 with ld = n rounded up to even (16-B rows)."""
+    torch = _torch()
+    ld = n + (n & 1)
+    return torch.empty((6, max(ld, 2)), dtype=torch.float64, device=device)
+
+
+def _bunch_args(z, n=None):
+    if z.dtype.itemsize != 8 or z.dim() != 2 or z.shape[0] != 6 or z.stride(1) != 1:
+        raise TypeError("bunch must be a (6, ld) float64 tensor with unit column stride")
+    ld = z.stride(0)
+    n = z.shape[1] if n is None else n
+    return C.c_void_p(z.data_ptr()), n, ld
+
+
+def element(e) -> Element:
+    """From a workloads.Element / workloads.Stage description."""
+    if hasattr(e, "kind"):
+        return Element(_KIND[e.kind], 0, float(e.L), float(e.k), float(e.angle), float(e.f), 0.0, 0.0)
+    return Element(STAGE, int(e.nsub), float(e.L), 0.0, 0.0, 0.0, float(e.n0_m3), float(e.dE_MeV))
+
+
+# ------------------------------------------------------------------ verbs
+def fill_gaussian(z, seed, mean, sigma, n=None, i0=0, stream=None):
+    ptr, n, ld = _bunch_args(z, n)
+    m = (C.c_double * 6)(*mean)
+    s = (C.c_double * 6)(*sigma)
+    _call("hbl_bunch_fill_gaussian", ptr, n, ld, seed, m, s, i0, stream or current_stream())
+
+
+class Lattice:
+    """Compiled sequence of linear elements for one reference energy."""
+
+    def __init__(self, elems, ref: Ref):
+        arr = (Element * max(1, len(elems)))(*[element(e) if not isinstance(e, Element) else e for e in elems])
+        h = C.c_void_p()
+        _call("hbl_lattice_create", arr, len(elems), C.byref(ref), C.byref(h))
+        self._h = h
+        L = C.c_double()
+        ne = C.c_int32()
+        _call("hbl_lattice_info", h, C.byref(L), C.byref(ne))
+        self.length, self.n_elem = L.value, ne.value
+
+    def push(self, z, ref: Ref, fused=True, n=None, stream=None):
+        ptr, n, ld = _bunch_args(z, n)
+        _call("hbl_push_lattice", ptr, n, ld, self._h, C.byref(ref), FUSED if fused else UNFUSED,
+              stream or current_stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.hbl_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def apply_stage(z, stage, ref: Ref, record=None, n=None, stream=None):
+    ptr, n, ld = _bunch_args(z, n)
+    el = stage if isinstance(stage, Element) else element(stage)
+    rp, rld = (None, 0)
+    if record is not None:
+        rp, _, rld = _bunch_args(record, n)
+    _call("hbl_apply_stage", ptr, n, ld, C.byref(el), C.byref(ref), rp, rld, stream or current_stream())
+
+
+def moments(z, n=None, stream=None):
+    ptr, n, ld = _bunch_args(z, n)
+    m = (C.c_double * 6)()
+    c = (C.c_double * 21)()
+    _call("hbl_moments", ptr, n, ld, m, c, stream or current_stream())
+    return list(m), list(c)
+
+
+def moments_async(z, out27, n=None, stream=None):
+    ptr, n, ld = _bunch_args(z, n)
+    _call("hbl_moments_async", ptr, n, ld, C.c_void_p(out27.data_ptr()), stream or current_stream())
+
+
+def emittances(cov21):
+    c = (C.c_double * 21)(*cov21)
+    e = (C.c_double * 3)()
+    _call("hbl_emittances", c, e)
+    return list(e)
+
+
+def compare(zs, zf, n=None, stream=None):
+    ps, n, ld = _bunch_args(zs, n)
+    pf, _, ldf = _bunch_args(zf, n)
+    if ldf != ld:
+        raise ValueError("compare: both bunches need the same leading dimension")
+    r, c, e = (C.c_double * 6)(), (C.c_double * 6)(), (C.c_double * 3)()
+    _call("hbl_compare", ps, pf, n, ld, r, c, e, stream or current_stream())
+    return list(r), list(c), list(e)

@@ -1,0 +1,159 @@
+"""GPU parity of the tracking path (fill, lattice, stage) against the CPU
+oracle, through the C ABI.  Tolerance: 1e-12 relative per coordinate
+(max_i |g - c| / max(|c|, rms(c))), oracle started from the GPU's own input
+bytes."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import PT, PX, X, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hbl():
+    from paper_2402_17248_amd import hbl as h
+    return h
+
+
+def sig():
+    return W.BunchSpec(1, 1).sigma
+
+
+def test_fill_matches_oracle(hbl, orc):
+    n = 10_001
+    z = hbl.new_bunch(n)
+    mean = (1e-6, 0.0, -2e-6, 0.0, 3e-5, 1e-4)
+    hbl.fill_gaussian(z, 42, mean, sig(), n=n)
+    g = to_host(z, n)
+    c = orc.fill_gaussian(n, 42, mean, sig())
+    err = np.abs(g - c) / np.array(sig())[:, None]
+    assert err.max() < 1e-14
+    # pieces with an index offset reproduce the same particles
+    z2 = hbl.new_bunch(1000)
+    hbl.fill_gaussian(z2, 42, mean, sig(), n=1000, i0=5000)
+    assert np.array_equal(to_host(z2, 1000), g[:, 5000:6000])
+
+
+def test_fill_full_size_sampled(hbl, orc):
+    n = 25_000_000
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, W.c5_chain().bunch.seed, (0.0,) * 6, sig(), n=n)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(n, 100_000, replace=False))
+    idx[-1] = n - 1
+    torch = __import__("torch")
+    g = z[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    c = orc.fill_gaussian(0, W.c5_chain().bunch.seed, (0.0,) * 6, sig(), idx=idx)
+    assert (np.abs(g - c) / np.array(sig())[:, None]).max() < 1e-14
+
+
+def fill_pair(hbl, orc, n, seed):
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, seed, (0.0,) * 6, sig(), n=n)
+    return z, to_host(z, n)
+
+
+@pytest.mark.parametrize("n", [1, 63, 10_000, 10_001])
+def test_fodo_parity(hbl, orc, n):
+    wl = W.c1_fodo(n=n)
+    z, c = fill_pair(hbl, orc, n, wl.bunch.seed)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    lat = hbl.Lattice(wl.beamline[0], ref)
+    hbl_ref = ref.copy()
+    lat.push(z, hbl_ref, fused=True, n=n)
+    g = to_host(z, n)
+    oref = orc.Ref.from_energy(wl.E_MeV)
+    orc.push(c, wl.beamline[0], oref)
+    assert rel_err(g, c).max() < TOL
+    assert abs(hbl_ref.s - oref.s) < 1e-15 and hbl_ref.gamma == ref.gamma
+
+
+def test_lattice58_fused_equals_unfused_and_oracle(hbl, orc):
+    wl = W.c2_fused()
+    n = wl.bunch.n
+    z, c0 = fill_pair(hbl, orc, n, wl.bunch.seed)
+    zu = z.clone()
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    lat = hbl.Lattice(wl.beamline[0], ref)
+    assert lat.n_elem == 58
+    lat.push(z, ref.copy(), fused=True, n=n)
+    lat.push(zu, ref.copy(), fused=False, n=n)
+    g = to_host(z, n)
+    gu = to_host(zu, n)
+    assert np.array_equal(g, gu)
+    rng = np.random.default_rng(1)
+    cols = np.sort(rng.choice(n, 100_000, replace=False))
+    c = np.ascontiguousarray(c0[:, cols])
+    orc.push(c, wl.beamline[0], orc.Ref.from_energy(wl.E_MeV))
+    assert rel_err(g[:, cols], c).max() < TOL
+
+
+def test_zero_particles_is_noop(hbl):
+    z = hbl.new_bunch(4)
+    before = z.clone()
+    ref = hbl.Ref.from_energy(1000.0)
+    hbl.fill_gaussian(z, 1, (0.0,) * 6, sig(), n=0)
+    lat = hbl.Lattice(W.fodo_cell(), ref)
+    lat.push(z, ref, n=0)
+    hbl.apply_stage(z, W.plasma_stage(), ref, n=0)
+    torch = __import__("torch")
+    torch.cuda.synchronize()
+    assert torch.equal(z, before)
+    assert abs(ref.gamma - 10000.0 / hbl.MEC2_MEV) < 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 2001])
+def test_stage_parity_with_record(hbl, orc, n):
+    wl = W.c3_stage(n=n)
+    z, c = fill_pair(hbl, orc, n, wl.bunch.seed)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    T1 = hbl.Lattice(wl.beamline[0], ref)
+    T1.push(z, ref, n=n)
+    rec = hbl.new_bunch(n)
+    hbl.apply_stage(z, wl.beamline[1], ref, record=rec, n=n)
+    T2 = hbl.Lattice(wl.beamline[2], ref)
+    T2.push(z, ref, n=n)
+    g = to_host(z, n)
+    r = to_host(rec, n)
+    oref = orc.Ref.from_energy(wl.E_MeV)
+    orc.push(c, wl.beamline[0], oref)
+    assert rel_err(r, c).max() < TOL            # the record holds the stage input
+    orc.push(c, [wl.beamline[1]], oref)
+    orc.push(c, wl.beamline[2], oref)
+    assert rel_err(g, c).max() < TOL
+    assert abs(ref.gamma / oref.gamma - 1) < 1e-15 and abs(ref.s - oref.s) < 1e-14
+
+
+def test_stage_full_size_sampled(hbl, orc):
+    wl = W.c3_stage()
+    n = wl.bunch.n
+    z, c0 = fill_pair(hbl, orc, n, wl.bunch.seed)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    for seg in wl.beamline:
+        if isinstance(seg, list):
+            hbl.Lattice(seg, ref).push(z, ref, n=n)
+        else:
+            hbl.apply_stage(z, seg, ref, n=n)
+    g = to_host(z, n)
+    cols = np.sort(np.random.default_rng(2).choice(n, 3000, replace=False))
+    c = np.ascontiguousarray(c0[:, cols])
+    orc.track(c, wl.beamline, orc.Ref.from_energy(wl.E_MeV))
+    assert rel_err(g[:, cols], c).max() < TOL
+
+
+@pytest.mark.parametrize("nsub,dE", [(1, 9000.0), (7, 9000.0), (2000, 0.0), (50, -500.0)])
+def test_stage_edge_cases(hbl, orc, nsub, dE):
+    """One substep (Newton path skipped), few substeps (large relative
+    gamma change: divide path), no energy gain, deceleration."""
+    n = 513
+    z, c = fill_pair(hbl, orc, n, 5)
+    st = W.Stage(L=0.3, n0_m3=1e23, dE_MeV=dE, nsub=nsub)
+    ref = hbl.Ref.from_energy(1000.0)
+    hbl.apply_stage(z, st, ref, n=n)
+    oref = orc.Ref.from_energy(1000.0)
+    orc.push(c, [st], oref)
+    assert rel_err(to_host(z, n), c).max() < TOL
