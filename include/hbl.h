@@ -159,6 +159,88 @@ hbl_status hbl_emittances(const double cov21[21], double eps3[3]);
 hbl_status hbl_compare(const double* zs, const double* zf, int64_t n, int64_t ld, double rms6[6],
                        double centroid6[6], double eps_rel3[3], hbl_stream stream);
 
+/* ---------------------------------------------------------------- surrogate */
+
+/* Neural-network stage surrogate (§3): the feed-forward network of Eq. (3),
+ * F = L_H o tanh o ... o tanh o L_0, L_i(x) = A_i x + b_i, acting on the six
+ * coordinates normalised per direction by the mean and standard deviation of
+ * the training inputs and outputs (§3); trained on the mean-squared error of
+ * Eq. (4) with Adam.  The kernels support the shape {6, 64, 3, 6} (three
+ * hidden layers of 64).  Dense layers run on the matrix cores in bf16 with
+ * FP32 accumulation; tanh and normalisation in FP32/FP64; the output layer
+ * result stays FP32 and is de-normalised in FP64.  FP32 master parameters,
+ * flat layout A_0 (64x6, row-major [out][in]), b_0, A_1, b_1, A_2, b_2, A_3
+ * (6x64), b_3: 9158 floats. */
+typedef struct hbl_surrogate hbl_surrogate;
+typedef struct hbl_mlp_shape {
+    int32_t n_in, width, hidden, n_out;
+} hbl_mlp_shape;
+
+/* Training recipe.  batch: multiple of 64; epochs >= 0; max_steps < 0 = no
+ * limit, else training stops after that many optimizer steps; the first
+ * round(train_frac * n_pairs) pairs train, the rest test (§3: 70/30); each
+ * epoch visits the training pairs in a Fisher-Yates order (Philox4x32-10,
+ * key shuffle_seed, counter (i/4, epoch, 'SHUF'), word i%4, j = floor(r (i+1)
+ * / 2^32)) in batches, dropping the last partial batch. */
+typedef struct hbl_train_cfg {
+    int32_t batch;
+    int32_t epochs;
+    int64_t max_steps;
+    float lr, beta1, beta2, eps;
+    double train_frac;
+    uint64_t shuffle_seed;
+} hbl_train_cfg;
+
+/* Create a surrogate with parameters U(-1/sqrt(fan_in), 1/sqrt(fan_in)):
+ * parameter p takes word 0 of Philox4x32-10 block (p, 0, 0, 'MLPI') keyed by
+ * init_seed, u = (word >> 8) 2^-24, value (2u - 1) / sqrt(fan_in).
+ * Synchronous.  Only shape {6, 64, 3, 6} is accepted. */
+hbl_status hbl_surrogate_create(const hbl_mlp_shape* shape, uint64_t init_seed, hbl_surrogate** out);
+hbl_status hbl_surrogate_destroy(hbl_surrogate* m);
+/* Number of FP32 parameters (9158). */
+hbl_status hbl_surrogate_num_params(const hbl_surrogate* m, int64_t* n);
+/* SYNC.  Copy the FP32 master parameters to / from host memory (n floats). */
+hbl_status hbl_surrogate_get_params(const hbl_surrogate* m, float* host, int64_t n);
+hbl_status hbl_surrogate_set_params(hbl_surrogate* m, const float* host, int64_t n);
+/* Normalisation: norm24 = mean_in[6], sd_in[6], mean_out[6], sd_out[6]
+ * (host FP64; sd > 0).  Training sets it from the training split. */
+hbl_status hbl_surrogate_get_norm(const hbl_surrogate* m, double norm24[24]);
+hbl_status hbl_surrogate_set_norm(hbl_surrogate* m, const double norm24[24]);
+/* Declare the stage the surrogate replaces: applying it moves the reference
+ * particle as the stage would (gamma by dE/mass, s by L).  at_entry->gamma is
+ * the entry energy it was trained for. */
+hbl_status hbl_surrogate_set_stage(hbl_surrogate* m, const hbl_element* stage, const hbl_ref* at_entry);
+
+/* Train on n_pairs (input, output) pairs (zin, zout: DEVICE bunches, same
+ * ld; e.g. recorded by hbl_apply_stage).  Computes the normalisation from the
+ * training split, resets the Adam state, then runs cfg->epochs epochs
+ * entirely on the device (forward, MSE, backward, Adam and the per-epoch test
+ * loss are this library's kernels).  SYNC at the end.  loss_log (host,
+ * nullable, 2*epochs floats): mean training-batch loss and test loss per
+ * epoch, in normalised units. */
+hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double* zout, int64_t n_pairs,
+                               int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream);
+
+/* SYNC.  Loss and gradient of one batch at the current parameters and
+ * normalisation, without updating: idx (host, batch int32 indices into the
+ * pairs, batch a multiple of 64), grad (host, 9158 floats), loss (host). */
+hbl_status hbl_surrogate_loss_grad(hbl_surrogate* m, const double* zin, const double* zout, int64_t ld,
+                                   const int32_t* idx, int32_t batch, float* grad, double* loss,
+                                   hbl_stream stream);
+
+/* ASYNC.  Apply the surrogate to the bunch in place (inference, §4.3): the
+ * stage it stands for, taken by the network; advances ref like the stage when
+ * one was declared (ref->gamma must then equal the declared entry gamma).
+ * Needs a normalisation (set or trained). */
+hbl_status hbl_surrogate_apply(double* z, int64_t n, int64_t ld, const hbl_surrogate* m, hbl_ref* ref,
+                               hbl_stream stream);
+
+/* Save / load the model (shape, normalisation, stage, FP32 parameters, Adam
+ * moments and step) to a binary file with a checksum.  HBL_EIO on I/O or
+ * format errors. */
+hbl_status hbl_surrogate_save(const hbl_surrogate* m, const char* path);
+hbl_status hbl_surrogate_load(const char* path, hbl_surrogate** out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -529,3 +529,525 @@ hbl_status hbl_compare(const double* zs, const double* zf, int64_t n, int64_t ld
 }
 
 }  // extern "C"
+
+// =================================================================== surrogate
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11) on the host: parameter initialisation
+// and the per-epoch Fisher-Yates orders.
+void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Fisher-Yates from the identity: for i = n-1..1 swap i and
+// j = floor(r (i+1) / 2^32), r = word i%4 of block (i/4, epoch, 'SHUF').
+void epoch_order(int32_t* perm, int64_t n, uint64_t seed, int64_t epoch) {
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t w[4] = {0, 0, 0, 0};
+    int64_t blk = -1;
+    for (int64_t i = n - 1; i >= 1; --i) {
+        if ((i >> 2) != blk) {
+            blk = i >> 2;
+            w[0] = (uint32_t)blk;
+            w[1] = (uint32_t)((uint64_t)blk >> 32);
+            w[2] = (uint32_t)epoch;
+            w[3] = 0x53485546u;
+            philox_host(w, k0, k1);
+        }
+        const uint64_t j = ((uint64_t)w[i & 3] * (uint64_t)(i + 1)) >> 32;
+        const int32_t t = perm[i];
+        perm[i] = perm[j];
+        perm[j] = t;
+    }
+}
+
+constexpr int kMlpParams = 9158;
+constexpr uint64_t kFileMagic = 0x31534C42484C4248ull;  // "HBLHBLS1"
+
+}  // namespace
+
+struct hbl_surrogate {
+    int device;
+    hbl_mlp_shape shape;
+    float* d_params;
+    float* d_m;
+    float* d_v;
+    uint32_t* d_img;
+    double norm[24];
+    bool has_norm;
+    int64_t step;
+    bool has_stage;
+    double dE_MeV, L, gamma_in;
+    // training scratch, allocated on first use
+    float* d_part;
+    float* d_loss_part;
+    double* d_eval_part;
+    double* d_loss_acc;
+    int32_t part_blocks;
+    int32_t loss_slots;
+};
+
+namespace {
+
+void sur_free(hbl_surrogate* m) {
+    if (!m) return;
+    void* ptrs[] = {m->d_params, m->d_m, m->d_v, m->d_img, m->d_part, m->d_loss_part, m->d_eval_part, m->d_loss_acc};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+hbl_status sur_alloc(hbl_surrogate** out, const hbl_mlp_shape* shape) {
+    hbl_surrogate* m = new (std::nothrow) hbl_surrogate();
+    if (!m) { set_error(HBL_ENOMEM, "surrogate: out of host memory"); return HBL_ENOMEM; }
+    memset(m, 0, sizeof *m);
+    m->shape = *shape;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        set_error(HBL_EHIP, "surrogate: no HIP device");
+        return HBL_EHIP;
+    }
+    const size_t pb = sizeof(float) * kMlpParams;
+    if (hipMalloc((void**)&m->d_params, pb) != hipSuccess || hipMalloc((void**)&m->d_m, pb) != hipSuccess ||
+        hipMalloc((void**)&m->d_v, pb) != hipSuccess ||
+        hipMalloc((void**)&m->d_img, sizeof(uint32_t) * mlp_image_words()) != hipSuccess) {
+        sur_free(m);
+        set_error(HBL_ENOMEM, "surrogate: device allocation failed");
+        return HBL_ENOMEM;
+    }
+    if (hipMemset(m->d_m, 0, pb) != hipSuccess || hipMemset(m->d_v, 0, pb) != hipSuccess) {
+        sur_free(m);
+        set_error(HBL_EHIP, "surrogate: device init failed");
+        return HBL_EHIP;
+    }
+    *out = m;
+    return HBL_OK;
+}
+
+hbl_status check_shape(const hbl_mlp_shape* sh) {
+    HBL_REQUIRE(sh, "surrogate: NULL shape");
+    HBL_REQUIRE(sh->n_in == 6 && sh->width == 64 && sh->hidden == 3 && sh->n_out == 6,
+                "surrogate: shape {%d,%d,%d,%d} not supported (kernels implement {6,64,3,6})", sh->n_in,
+                sh->width, sh->hidden, sh->n_out);
+    return HBL_OK;
+}
+
+hbl_status check_norm(const double* n) {
+    for (int j = 0; j < 24; ++j) HBL_REQUIRE(isfinite(n[j]), "surrogate: non-finite normalisation entry %d", j);
+    for (int j = 0; j < 6; ++j)
+        HBL_REQUIRE(n[6 + j] > 0.0 && n[18 + j] > 0.0, "surrogate: normalisation sd[%d] must be > 0", j);
+    return HBL_OK;
+}
+
+hbl_status repack(hbl_surrogate* m, hipStream_t s) {
+    HBL_HIP(launch_mlp_pack(m->d_params, m->d_img, s));
+    return HBL_OK;
+}
+
+hbl_status ensure_train_scratch(hbl_surrogate* m, int32_t blocks, int32_t loss_slots) {
+    if (m->part_blocks < blocks) {
+        if (m->d_part) (void)hipFree(m->d_part);
+        if (m->d_loss_part) (void)hipFree(m->d_loss_part);
+        m->d_part = nullptr;
+        m->d_loss_part = nullptr;
+        m->part_blocks = 0;
+        if (hipMalloc((void**)&m->d_part, sizeof(float) * (size_t)blocks * kMlpParams) != hipSuccess ||
+            hipMalloc((void**)&m->d_loss_part, sizeof(float) * blocks) != hipSuccess) {
+            set_error(HBL_ENOMEM, "surrogate: training scratch allocation failed");
+            return HBL_ENOMEM;
+        }
+        m->part_blocks = blocks;
+    }
+    if (!m->d_eval_part) {
+        if (hipMalloc((void**)&m->d_eval_part, sizeof(double) * 512) != hipSuccess) {
+            set_error(HBL_ENOMEM, "surrogate: scratch allocation failed");
+            return HBL_ENOMEM;
+        }
+    }
+    if (m->loss_slots < loss_slots) {
+        if (m->d_loss_acc) (void)hipFree(m->d_loss_acc);
+        m->d_loss_acc = nullptr;
+        m->loss_slots = 0;
+        if (hipMalloc((void**)&m->d_loss_acc, sizeof(double) * loss_slots) != hipSuccess) {
+            set_error(HBL_ENOMEM, "surrogate: loss log allocation failed");
+            return HBL_ENOMEM;
+        }
+        m->loss_slots = loss_slots;
+    }
+    return HBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_surrogate_create(const hbl_mlp_shape* shape, uint64_t init_seed, hbl_surrogate** out) {
+    clear_error();
+    HBL_REQUIRE(out, "surrogate_create: NULL output handle");
+    *out = nullptr;
+    if (hbl_status st = check_shape(shape)) return st;
+    // U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for weights and biases
+    std::vector<float> p(kMlpParams);
+    const int fan[4] = {6, 64, 64, 64}, outs[4] = {64, 64, 64, 6};
+    int64_t off = 0;
+    for (int layer = 0; layer < 4; ++layer) {
+        const double bound = 1.0 / sqrt((double)fan[layer]);
+        const int64_t cnt = (int64_t)outs[layer] * (fan[layer] + 1);
+        for (int64_t q = 0; q < cnt; ++q, ++off) {
+            uint32_t c[4] = {(uint32_t)off, (uint32_t)((uint64_t)off >> 32), 0u, 0x4D4C5049u};
+            philox_host(c, (uint32_t)init_seed, (uint32_t)(init_seed >> 32));
+            const double u = (double)(c[0] >> 8) * (1.0 / 16777216.0);
+            p[off] = (float)((2.0 * u - 1.0) * bound);
+        }
+    }
+    hbl_surrogate* m = nullptr;
+    if (hbl_status st = sur_alloc(&m, shape)) return st;
+    if (hipMemcpy(m->d_params, p.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice) != hipSuccess) {
+        sur_free(m);
+        set_error(HBL_EHIP, "surrogate_create: upload failed");
+        return HBL_EHIP;
+    }
+    if (hbl_status st = repack(m, nullptr)) { sur_free(m); return st; }
+    if (hipDeviceSynchronize() != hipSuccess) { sur_free(m); set_error(HBL_EHIP, "surrogate_create: pack failed"); return HBL_EHIP; }
+    *out = m;
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_destroy(hbl_surrogate* m) {
+    clear_error();
+    sur_free(m);
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_num_params(const hbl_surrogate* m, int64_t* n) {
+    clear_error();
+    HBL_REQUIRE(m && n, "surrogate_num_params: NULL argument");
+    *n = kMlpParams;
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_get_params(const hbl_surrogate* m, float* host, int64_t n) {
+    clear_error();
+    HBL_REQUIRE(m && host, "surrogate_get_params: NULL argument");
+    HBL_REQUIRE(n == kMlpParams, "surrogate_get_params: n = %lld, need %d", (long long)n, kMlpParams);
+    HBL_HIP(hipDeviceSynchronize());
+    HBL_HIP(hipMemcpy(host, m->d_params, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_set_params(hbl_surrogate* m, const float* host, int64_t n) {
+    clear_error();
+    HBL_REQUIRE(m && host, "surrogate_set_params: NULL argument");
+    HBL_REQUIRE(n == kMlpParams, "surrogate_set_params: n = %lld, need %d", (long long)n, kMlpParams);
+    for (int64_t q = 0; q < n; ++q) HBL_REQUIRE(isfinite(host[q]), "surrogate_set_params: non-finite parameter %lld", (long long)q);
+    HBL_HIP(hipDeviceSynchronize());
+    HBL_HIP(hipMemcpy(m->d_params, host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    if (hbl_status st = repack(m, nullptr)) return st;
+    HBL_HIP(hipDeviceSynchronize());
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_get_norm(const hbl_surrogate* m, double norm24[24]) {
+    clear_error();
+    HBL_REQUIRE(m && norm24, "surrogate_get_norm: NULL argument");
+    if (!m->has_norm) { set_error(HBL_ESTATE, "surrogate_get_norm: no normalisation set or trained"); return HBL_ESTATE; }
+    memcpy(norm24, m->norm, sizeof m->norm);
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_set_norm(hbl_surrogate* m, const double norm24[24]) {
+    clear_error();
+    HBL_REQUIRE(m && norm24, "surrogate_set_norm: NULL argument");
+    if (hbl_status st = check_norm(norm24)) return st;
+    memcpy(m->norm, norm24, sizeof m->norm);
+    m->has_norm = true;
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_set_stage(hbl_surrogate* m, const hbl_element* stage, const hbl_ref* at_entry) {
+    clear_error();
+    HBL_REQUIRE(m && stage, "surrogate_set_stage: NULL argument");
+    HBL_REQUIRE(stage->kind == HBL_STAGE, "surrogate_set_stage: element is not a stage");
+    HBL_REQUIRE(finite_pos(stage->L) && isfinite(stage->dE_MeV), "surrogate_set_stage: bad L or dE");
+    if (hbl_status st = check_ref(at_entry)) return st;
+    HBL_REQUIRE(at_entry->gamma + stage->dE_MeV / at_entry->mass_MeV > 1.0, "surrogate_set_stage: exit gamma must exceed 1");
+    m->has_stage = true;
+    m->dE_MeV = stage->dE_MeV;
+    m->L = stage->L;
+    m->gamma_in = at_entry->gamma;
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_apply(double* z, int64_t n, int64_t ld, const hbl_surrogate* m, hbl_ref* ref,
+                               hbl_stream stream) {
+    clear_error();
+    if (hbl_status st = check_bunch(z, n, ld, "surrogate_apply")) return st;
+    HBL_REQUIRE(m, "surrogate_apply: NULL surrogate");
+    if (!m->has_norm) { set_error(HBL_ESTATE, "surrogate_apply: no normalisation set or trained"); return HBL_ESTATE; }
+    if (m->has_stage) {
+        if (hbl_status st = check_ref(ref)) return st;
+        HBL_REQUIRE(fabs(ref->gamma / m->gamma_in - 1.0) < 1e-12,
+                    "surrogate_apply: reference gamma %.17g differs from the trained entry gamma %.17g",
+                    ref->gamma, m->gamma_in);
+    }
+    if (n > 0) HBL_HIP(launch_mlp_infer(z, n, ld, m->d_img, m->norm, (hipStream_t)stream));
+    if (m->has_stage) {
+        ref->gamma += m->dE_MeV / ref->mass_MeV;
+        ref->s += m->L;
+    }
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_loss_grad(hbl_surrogate* m, const double* zin, const double* zout, int64_t ld,
+                                   const int32_t* idx, int32_t batch, float* grad, double* loss,
+                                   hbl_stream stream) {
+    clear_error();
+    HBL_REQUIRE(m && idx && grad && loss, "surrogate_loss_grad: NULL argument");
+    HBL_REQUIRE(batch >= 64 && batch % 64 == 0 && batch <= (1 << 20), "surrogate_loss_grad: batch %d must be a positive multiple of 64", batch);
+    if (hbl_status st = check_bunch(zin, 1, ld, "surrogate_loss_grad(in)")) return st;
+    if (hbl_status st = check_bunch(zout, 1, ld, "surrogate_loss_grad(out)")) return st;
+    HBL_REQUIRE(zin && zout, "surrogate_loss_grad: NULL pairs");
+    for (int32_t q = 0; q < batch; ++q) HBL_REQUIRE(idx[q] >= 0 && idx[q] < ld, "surrogate_loss_grad: index %d out of range", idx[q]);
+    if (!m->has_norm) { set_error(HBL_ESTATE, "surrogate_loss_grad: no normalisation set"); return HBL_ESTATE; }
+    const int32_t nb = batch / 64;
+    if (hbl_status st = ensure_train_scratch(m, nb, 2)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* d_idx = nullptr;
+    float* d_grad = nullptr;
+    HBL_HIP(hipMalloc((void**)&d_idx, sizeof(int32_t) * batch));
+    if (hipMalloc((void**)&d_grad, sizeof(float) * kMlpParams) != hipSuccess) {
+        (void)hipFree(d_idx);
+        set_error(HBL_ENOMEM, "surrogate_loss_grad: allocation failed");
+        return HBL_ENOMEM;
+    }
+    hbl_status st = HBL_OK;
+    std::vector<float> lp(nb);
+    hipError_t e = hipMemcpyAsync(d_idx, idx, sizeof(int32_t) * batch, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_train_step(zin, zout, ld, d_idx, batch, m->d_img, m->d_part, m->d_loss_part, m->norm, s);
+    if (e == hipSuccess) e = launch_grad_sum(m->d_part, nb, d_grad, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(grad, d_grad, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lp.data(), m->d_loss_part, sizeof(float) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error(HBL_EHIP, "surrogate_loss_grad: %s", hipGetErrorString(e));
+        st = HBL_EHIP;
+    } else {
+        double sum = 0.0;
+        for (int32_t b = 0; b < nb; ++b) sum += lp[b];
+        *loss = sum / ((double)batch * 6.0);
+    }
+    (void)hipFree(d_idx);
+    (void)hipFree(d_grad);
+    return st;
+}
+
+hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double* zout, int64_t n_pairs,
+                               int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream) {
+    clear_error();
+    HBL_REQUIRE(m && cfg, "surrogate_train: NULL argument");
+    if (hbl_status st = check_bunch(zin, n_pairs, ld, "surrogate_train(in)")) return st;
+    if (hbl_status st = check_bunch(zout, n_pairs, ld, "surrogate_train(out)")) return st;
+    HBL_REQUIRE(cfg->batch >= 64 && cfg->batch % 64 == 0 && cfg->batch <= (1 << 20),
+                "surrogate_train: batch %d must be a positive multiple of 64", cfg->batch);
+    HBL_REQUIRE(cfg->epochs >= 0 && cfg->epochs <= 1000000, "surrogate_train: bad epoch count");
+    HBL_REQUIRE(isfinite(cfg->lr) && cfg->lr > 0, "surrogate_train: lr must be > 0");
+    HBL_REQUIRE(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1, "surrogate_train: betas must be in [0,1)");
+    HBL_REQUIRE(isfinite(cfg->eps) && cfg->eps > 0, "surrogate_train: eps must be > 0");
+    HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "surrogate_train: train_frac must be in (0, 1]");
+    HBL_REQUIRE(n_pairs <= INT32_MAX, "surrogate_train: at most 2^31-1 pairs");
+    const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
+    const int64_t n_test = n_pairs - n_train;
+    HBL_REQUIRE(n_train >= cfg->batch, "surrogate_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);
+    hipStream_t s = (hipStream_t)stream;
+    // normalisation from the training split (§3), FP64 compensated moments
+    double mi[6], ci[21], mo[6], co[21];
+    if (hbl_status st = hbl_moments(zin, n_train, ld, mi, ci, stream)) return st;
+    if (hbl_status st = hbl_moments(zout, n_train, ld, mo, co, stream)) return st;
+    double norm[24];
+    for (int j = 0; j < 6; ++j) {
+        const int d = j * 6 - j * (j - 1) / 2;
+        norm[j] = mi[j];
+        norm[6 + j] = sqrt(ci[d]);
+        norm[12 + j] = mo[j];
+        norm[18 + j] = sqrt(co[d]);
+    }
+    if (hbl_status st = check_norm(norm)) {
+        set_error(HBL_EINVAL, "surrogate_train: a coordinate has zero spread in the training split");
+        return st;
+    }
+    memcpy(m->norm, norm, sizeof norm);
+    m->has_norm = true;
+    const int32_t nb = cfg->batch / 64;
+    const int64_t steps_per_epoch = n_train / cfg->batch;
+    if (hbl_status st = ensure_train_scratch(m, nb, 2 * (cfg->epochs > 0 ? cfg->epochs : 1))) return st;
+    // fresh Adam state
+    HBL_HIP(hipMemsetAsync(m->d_m, 0, sizeof(float) * kMlpParams, s));
+    HBL_HIP(hipMemsetAsync(m->d_v, 0, sizeof(float) * kMlpParams, s));
+    HBL_HIP(hipMemsetAsync(m->d_loss_acc, 0, sizeof(double) * 2 * (cfg->epochs > 0 ? cfg->epochs : 1), s));
+    if (hbl_status st = repack(m, s)) return st;
+    m->step = 0;
+    // double-buffered epoch orders: host pinned -> device
+    int32_t* h_perm[2] = {nullptr, nullptr};
+    int32_t* d_perm[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hbl_status st = HBL_OK;
+    auto fail = [&](hbl_status code, const char* what, hipError_t e) {
+        set_error(code, "surrogate_train: %s: %s", what, hipGetErrorString(e));
+        st = code;
+    };
+    for (int k = 0; k < 2 && st == HBL_OK; ++k) {
+        hipError_t e = hipHostMalloc((void**)&h_perm[k], sizeof(int32_t) * n_train, 0);
+        if (e == hipSuccess) e = hipMalloc((void**)&d_perm[k], sizeof(int32_t) * n_train);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) fail(HBL_ENOMEM, "order buffers", e);
+    }
+    std::vector<int64_t> steps_done(cfg->epochs > 0 ? cfg->epochs : 1, 0);
+    for (int64_t ep = 0; ep < cfg->epochs && st == HBL_OK; ++ep) {
+        const int k = (int)(ep & 1);
+        hipError_t e = hipEventSynchronize(ev[k]);   // the copy two epochs ago has finished
+        if (e != hipSuccess) { fail(HBL_EHIP, "event wait", e); break; }
+        epoch_order(h_perm[k], n_train, cfg->shuffle_seed, ep);
+        e = hipMemcpyAsync(d_perm[k], h_perm[k], sizeof(int32_t) * n_train, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[k], s);
+        if (e != hipSuccess) { fail(HBL_EHIP, "order upload", e); break; }
+        for (int64_t step = 0; step < steps_per_epoch; ++step) {
+            if (cfg->max_steps >= 0 && m->step >= cfg->max_steps) break;
+            m->step += 1;
+            e = launch_train_step(zin, zout, ld, d_perm[k] + step * cfg->batch, cfg->batch, m->d_img,
+                                  m->d_part, m->d_loss_part, m->norm, s);
+            if (e == hipSuccess)
+                e = launch_train_adam(m->d_params, m->d_m, m->d_v, m->d_part, nb, m->d_loss_part,
+                                      m->d_loss_acc + 2 * ep, 1.0 / ((double)cfg->batch * 6.0), m->step,
+                                      cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, s);
+            if (e == hipSuccess) e = launch_mlp_pack(m->d_params, m->d_img, s);
+            if (e != hipSuccess) { fail(HBL_EHIP, "step launch", e); break; }
+            steps_done[ep] += 1;
+        }
+        if (st != HBL_OK) break;
+        if (n_test > 0) {
+            e = launch_eval_loss(zin, zout, ld, n_train, n_test, m->d_img, m->norm, m->d_eval_part,
+                                 m->d_loss_acc + 2 * ep + 1, s);
+            if (e != hipSuccess) { fail(HBL_EHIP, "test loss launch", e); break; }
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (st == HBL_OK && e != hipSuccess) fail(HBL_EHIP, "training", e);
+    if (st == HBL_OK && loss_log && cfg->epochs > 0) {
+        std::vector<double> acc(2 * cfg->epochs);
+        e = hipMemcpy(acc.data(), m->d_loss_acc, sizeof(double) * acc.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) fail(HBL_EHIP, "loss readback", e);
+        for (int64_t ep = 0; ep < cfg->epochs && st == HBL_OK; ++ep) {
+            loss_log[2 * ep] = steps_done[ep] ? (float)(acc[2 * ep] / (double)steps_done[ep]) : 0.0f;
+            loss_log[2 * ep + 1] = (float)acc[2 * ep + 1];
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+        if (d_perm[k]) (void)hipFree(d_perm[k]);
+        if (h_perm[k]) (void)hipHostFree(h_perm[k]);
+    }
+    return st;
+}
+
+hbl_status hbl_surrogate_save(const hbl_surrogate* m, const char* path) {
+    clear_error();
+    HBL_REQUIRE(m && path, "surrogate_save: NULL argument");
+    std::vector<float> blob(3 * (size_t)kMlpParams);
+    HBL_HIP(hipDeviceSynchronize());
+    HBL_HIP(hipMemcpy(blob.data(), m->d_params, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    HBL_HIP(hipMemcpy(blob.data() + kMlpParams, m->d_m, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    HBL_HIP(hipMemcpy(blob.data() + 2 * kMlpParams, m->d_v, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    struct {
+        uint64_t magic;
+        int32_t shape[4];
+        int32_t has_norm, has_stage;
+        int64_t step;
+        double norm[24];
+        double dE_MeV, L, gamma_in;
+    } hdr;
+    memset(&hdr, 0, sizeof hdr);
+    hdr.magic = kFileMagic;
+    hdr.shape[0] = m->shape.n_in; hdr.shape[1] = m->shape.width; hdr.shape[2] = m->shape.hidden; hdr.shape[3] = m->shape.n_out;
+    hdr.has_norm = m->has_norm;
+    hdr.has_stage = m->has_stage;
+    hdr.step = m->step;
+    memcpy(hdr.norm, m->norm, sizeof hdr.norm);
+    hdr.dE_MeV = m->dE_MeV; hdr.L = m->L; hdr.gamma_in = m->gamma_in;
+    // FNV-1a 64 over header and payload
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t nbytes) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t q = 0; q < nbytes; ++q) { h ^= c[q]; h *= 1099511628211ull; }
+    };
+    mix(&hdr, sizeof hdr);
+    mix(blob.data(), blob.size() * sizeof(float));
+    FILE* f = fopen(path, "wb");
+    if (!f) { set_error(HBL_EIO, "surrogate_save: cannot open %s", path); return HBL_EIO; }
+    bool ok = fwrite(&hdr, sizeof hdr, 1, f) == 1 && fwrite(blob.data(), sizeof(float), blob.size(), f) == blob.size() &&
+              fwrite(&h, sizeof h, 1, f) == 1;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) { set_error(HBL_EIO, "surrogate_save: write failed for %s", path); return HBL_EIO; }
+    return HBL_OK;
+}
+
+hbl_status hbl_surrogate_load(const char* path, hbl_surrogate** out) {
+    clear_error();
+    HBL_REQUIRE(path && out, "surrogate_load: NULL argument");
+    *out = nullptr;
+    struct {
+        uint64_t magic;
+        int32_t shape[4];
+        int32_t has_norm, has_stage;
+        int64_t step;
+        double norm[24];
+        double dE_MeV, L, gamma_in;
+    } hdr;
+    std::vector<float> blob(3 * (size_t)kMlpParams);
+    uint64_t stored = 0;
+    FILE* f = fopen(path, "rb");
+    if (!f) { set_error(HBL_EIO, "surrogate_load: cannot open %s", path); return HBL_EIO; }
+    bool ok = fread(&hdr, sizeof hdr, 1, f) == 1 && fread(blob.data(), sizeof(float), blob.size(), f) == blob.size() &&
+              fread(&stored, sizeof stored, 1, f) == 1;
+    fclose(f);
+    if (!ok) { set_error(HBL_EIO, "surrogate_load: %s is truncated", path); return HBL_EIO; }
+    if (hdr.magic != kFileMagic) { set_error(HBL_EIO, "surrogate_load: %s is not a surrogate file", path); return HBL_EIO; }
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t nbytes) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t q = 0; q < nbytes; ++q) { h ^= c[q]; h *= 1099511628211ull; }
+    };
+    mix(&hdr, sizeof hdr);
+    mix(blob.data(), blob.size() * sizeof(float));
+    if (h != stored) { set_error(HBL_EIO, "surrogate_load: checksum mismatch in %s", path); return HBL_EIO; }
+    hbl_mlp_shape sh = {hdr.shape[0], hdr.shape[1], hdr.shape[2], hdr.shape[3]};
+    if (hbl_status st = check_shape(&sh)) return st;
+    hbl_surrogate* m = nullptr;
+    if (hbl_status st = sur_alloc(&m, &sh)) return st;
+    hipError_t e = hipMemcpy(m->d_params, blob.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_m, blob.data() + kMlpParams, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_v, blob.data() + 2 * kMlpParams, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mlp_pack(m->d_params, m->d_img, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { sur_free(m); set_error(HBL_EHIP, "surrogate_load: upload failed: %s", hipGetErrorString(e)); return HBL_EHIP; }
+    m->has_norm = hdr.has_norm != 0;
+    memcpy(m->norm, hdr.norm, sizeof m->norm);
+    m->has_stage = hdr.has_stage != 0;
+    m->dE_MeV = hdr.dE_MeV; m->L = hdr.L; m->gamma_in = hdr.gamma_in;
+    m->step = hdr.step;
+    *out = m;
+    return HBL_OK;
+}
+
+}  // extern "C"

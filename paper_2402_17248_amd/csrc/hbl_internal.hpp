@@ -61,6 +61,24 @@ hipError_t launch_moments(const double* z, int64_t n, int64_t ld, double* ws, do
 hipError_t launch_diff2(const double* zs, const double* zf, int64_t n, int64_t ld, double* ws,
                         double* out6, hipStream_t s);
 
+// Surrogate network (tanh MLP 6-64-64-64-6).
+int mlp_nparams();
+int mlp_image_words();
+hipError_t launch_mlp_pack(const float* params, uint32_t* img, hipStream_t s);
+hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* img, const double* norm24,
+                            hipStream_t s);
+hipError_t launch_train_step(const double* zin, const double* zout, int64_t ld, const int32_t* idx,
+                             int32_t batch, const uint32_t* img, float* part, float* loss_part,
+                             const double* norm24, hipStream_t s);
+hipError_t launch_train_adam(float* p, float* m, float* v, const float* part, int32_t nb,
+                             const float* loss_part, double* loss_acc, double loss_scale, int64_t t,
+                             float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_grad_sum(const float* part, int32_t nb, float* grad, hipStream_t s);
+int eval_loss_blocks(int64_t n);
+hipError_t launch_eval_loss(const double* zin, const double* zout, int64_t ld, int64_t i0, int64_t n,
+                            const uint32_t* img, const double* norm24, double* part, double* out,
+                            hipStream_t s);
+
 // Per-device library workspace (grow-only, freed at exit).
 double* workspace(size_t bytes);
 

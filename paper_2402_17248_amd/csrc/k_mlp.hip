@@ -1,0 +1,753 @@
+// Surrogate network kernels for gfx950: the tanh MLP 6 -> 64 -> 64 -> 64 -> 6
+// of §3 Eq. (3), inference on FP64 bunches.  Dense layers run on the matrix
+// cores (v_mfma_f32_16x16x32_bf16: bf16 operands, FP32 accumulation); tanh,
+// normalisation and bf16 rounding run on the vector ALU.
+//
+// Matrix-core layout (16x16x32, one wavefront, lane l, g = l / 16):
+//   A (16 x 32): lane l holds row l % 16, k = 8g .. 8g+7
+//   B (32 x 16): lane l holds column l % 16, k = 8g .. 8g+7
+//   D (16 x 16): lane l holds column l % 16, rows 4g .. 4g+3
+// Layers are computed transposed, D^T = W X^T: the weights are the A operand
+// (resident in registers for the whole kernel), particles are the 16
+// columns.  A layer's D tiles (rows = output features 16mt + 4g + i) are the
+// next layer's B operand without any cross-lane movement, provided the next
+// layer's K slots are permuted to match: K-chunk c, slot 8g + j holds
+// feature 32c + 4g + j for j < 4 and 32c + 16 + 4g + (j - 4) for j >= 4.
+// The weight image below is built with that permutation.
+//
+// First layer: K = 6 is padded to 32; the padding carries a bf16 hi/lo split
+// of the FP32 network input and of the FP32 first-layer weights,
+// W x ~ W_hi x_hi + W_hi x_lo + W_lo x_hi (slots 0-5, 6-11, 12-17), so the
+// input keeps ~16 significant bits.  Hidden activations are bf16; the output
+// layer result stays FP32 and is de-normalised in FP64.
+#include "hbl_internal.hpp"
+
+namespace hbl {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kW = 64;      // hidden width
+constexpr int kIn = 6;      // phase-space dimension
+
+// ------------------------------------------------------------ bf16 helpers
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    // hardware round-to-nearest-even conversion of two FP32 values
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ float bf16_round(float a) {
+    return (float)(__bf16)a;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// tanh(a) = 1 - 2 / (2^(2 a log2 e) + 1): one exp2, one reciprocal (both
+// hardware approximations, ~1 ulp), saturating correctly for large |a|.
+__device__ __forceinline__ float tanh_f32(float a) {
+    const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);
+    const float r = __builtin_amdgcn_rcpf(e + 1.0f);
+    return fmaf(-2.0f, r, 1.0f);
+}
+
+// Feature held by K slot s = 8g + j of K-chunk c of a 64-wide layer input.
+__host__ __device__ __forceinline__ int perm_feature(int c, int g, int j) {
+    return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+// ------------------------------------------------------------ weight image
+// Word w of lane l at image[w * 64 + l] (lane-contiguous, coalesced loads):
+//   words   0.. 15  layer 0 A operands, M-tile mt: words 4mt .. 4mt+3
+//   words  16.. 47  layer 1 A operands, (mt, c): 16 + 8mt + 4c
+//   words  48.. 79  layer 2 A operands, (mt, c): 48 + 8mt + 4c
+//   words  80.. 87  layer 3 A operands, c: 80 + 4c
+//   words  88..103  layer 0 bias, M-tile mt rows 16mt + 4g + i: 88 + 4mt + i
+//   words 104..119  layer 1 bias
+//   words 120..135  layer 2 bias
+//   words 136..139  layer 3 bias (rows 4g + i < 6)
+// Transposed weights for back-propagation (training only), D^T = W^T E^T:
+//   words 140..155  W3^T, M-tile mt (layer-3 input features): 140 + 4mt;
+//                   K slot 8g + j (j < 4) <-> output row 4g + j, others 0
+//   words 156..187  W2^T, (mt, c): 156 + 8mt + 4c, K slots permuted as above
+//   words 188..219  W1^T, (mt, c): 188 + 8mt + 4c
+constexpr int kImgWords = 220;
+constexpr int kImgFwdWords = 140;
+
+// Flat FP32 parameter offsets (row-major [out][in] weights, then bias).
+constexpr int kOffW0 = 0, kOffB0 = 384, kOffW1 = 448, kOffB1 = 4544, kOffW2 = 4608,
+              kOffB2 = 8704, kOffW3 = 8768, kOffB3 = 9152;
+constexpr int kNParams = 9158;
+
+__global__ void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ img) {
+    const int l = threadIdx.x;  // one wavefront
+    const int r = l % 16, g = l / 16;
+    auto bfw = [](float v) { return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v); };
+    // layer 0: slots 0-5 W_hi, 6-11 W_hi, 12-17 W_lo, rest 0
+    for (int mt = 0; mt < 4; ++mt) {
+        const int m = 16 * mt + r;
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 8; ++j) {
+            const int s = 8 * g + j;
+            float v = 0.0f;
+            if (s < 18) {
+                const int f = s % 6;
+                const float wf = p[kOffW0 + m * kIn + f];
+                const float hi = bf16_round(wf);
+                v = (s < 12) ? hi : bf16_round(wf - hi);
+            }
+            w[j / 2] |= bfw(v) << (16 * (j & 1));
+        }
+        for (int q = 0; q < 4; ++q) img[(4 * mt + q) * 64 + l] = w[q];
+    }
+    // layers 1, 2
+    for (int layer = 1; layer <= 2; ++layer) {
+        const float* W = p + (layer == 1 ? kOffW1 : kOffW2);
+        const int base = layer == 1 ? 16 : 48;
+        for (int mt = 0; mt < 4; ++mt)
+            for (int c = 0; c < 2; ++c) {
+                const int m = 16 * mt + r;
+                uint32_t w[4] = {0, 0, 0, 0};
+                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(W[m * kW + perm_feature(c, g, j)]) << (16 * (j & 1));
+                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * c + q) * 64 + l] = w[q];
+            }
+    }
+    // layer 3: 6 output rows, rows 6..15 zero
+    for (int c = 0; c < 2; ++c) {
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 8; ++j) {
+            const float v = r < kIn ? p[kOffW3 + r * kW + perm_feature(c, g, j)] : 0.0f;
+            w[j / 2] |= bfw(v) << (16 * (j & 1));
+        }
+        for (int q = 0; q < 4; ++q) img[(80 + 4 * c + q) * 64 + l] = w[q];
+    }
+    // biases (FP32 bit patterns)
+    for (int layer = 0; layer < 3; ++layer) {
+        const float* b = p + (layer == 0 ? kOffB0 : layer == 1 ? kOffB1 : kOffB2);
+        for (int mt = 0; mt < 4; ++mt)
+            for (int i = 0; i < 4; ++i)
+                img[(88 + 16 * layer + 4 * mt + i) * 64 + l] = __float_as_uint(b[16 * mt + 4 * g + i]);
+    }
+    for (int i = 0; i < 4; ++i) {
+        const int row = 4 * g + i;
+        img[(136 + i) * 64 + l] = __float_as_uint(row < kIn ? p[kOffB3 + row] : 0.0f);
+    }
+    // transposed layer 3: A[m][8g + j] = W3[4g + j][m] for j < 4, 4g + j < 6
+    for (int mt = 0; mt < 4; ++mt) {
+        const int m = 16 * mt + r;
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j) {
+            const int row = 4 * g + j;
+            const float v = row < kIn ? p[kOffW3 + row * kW + m] : 0.0f;
+            w[j / 2] |= bfw(v) << (16 * (j & 1));
+        }
+        for (int q = 0; q < 4; ++q) img[(140 + 4 * mt + q) * 64 + l] = w[q];
+    }
+    // transposed layers 2, 1: A[m][slot] = W[perm_feature(c, g, j)][m]
+    for (int layer = 2; layer >= 1; --layer) {
+        const float* W = p + (layer == 1 ? kOffW1 : kOffW2);
+        const int base = layer == 2 ? 156 : 188;
+        for (int mt = 0; mt < 4; ++mt)
+            for (int c = 0; c < 2; ++c) {
+                const int m = 16 * mt + r;
+                uint32_t w[4] = {0, 0, 0, 0};
+                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(W[perm_feature(c, g, j) * kW + m]) << (16 * (j & 1));
+                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * c + q) * 64 + l] = w[q];
+            }
+    }
+}
+
+struct NormArgs {
+    double mu_in[6];
+    double inv_sd_in[6];
+    double mu_out[6];
+    double sd_out[6];
+};
+
+// Network state resident in registers for the whole kernel.
+struct Net {
+    u32x4 a0[4];
+    u32x4 a1[4][2];
+    u32x4 a2[4][2];
+    u32x4 a3[2];
+    f32x4 b0[4], b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ void load_net(const uint32_t* __restrict__ img, Net& net) {
+    const int l = threadIdx.x & 63;
+    auto ld4 = [&](int w) {
+        return u32x4{img[(w + 0) * 64 + l], img[(w + 1) * 64 + l], img[(w + 2) * 64 + l], img[(w + 3) * 64 + l]};
+    };
+    auto ldf4 = [&](int w) {
+        return f32x4{__uint_as_float(img[(w + 0) * 64 + l]), __uint_as_float(img[(w + 1) * 64 + l]),
+                     __uint_as_float(img[(w + 2) * 64 + l]), __uint_as_float(img[(w + 3) * 64 + l])};
+    };
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        net.a0[mt] = ld4(4 * mt);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            net.a1[mt][c] = ld4(16 + 8 * mt + 4 * c);
+            net.a2[mt][c] = ld4(48 + 8 * mt + 4 * c);
+        }
+        net.b0[mt] = ldf4(88 + 4 * mt);
+        net.b1[mt] = ldf4(104 + 4 * mt);
+        net.b2[mt] = ldf4(120 + 4 * mt);
+    }
+    net.a3[0] = ld4(80);
+    net.a3[1] = ld4(84);
+    net.b3 = ldf4(136);
+}
+
+// tanh of a layer's four D tiles, packed as the next layer's two B operands.
+__device__ __forceinline__ void activate(const f32x4 (&d)[4], u32x4 (&h)[2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const f32x4 p = d[2 * c], q = d[2 * c + 1];
+        h[c] = u32x4{pack_bf16x2(tanh_f32(p[0]), tanh_f32(p[1])), pack_bf16x2(tanh_f32(p[2]), tanh_f32(p[3])),
+                     pack_bf16x2(tanh_f32(q[0]), tanh_f32(q[1])), pack_bf16x2(tanh_f32(q[2]), tanh_f32(q[3]))};
+    }
+}
+
+// Forward of one 16-particle tile: B operand of layer 0 in, FP32 output tile
+// (rows 4g + i = output coordinate, column = particle) out.
+__device__ __forceinline__ f32x4 forward_tile(const Net& net, u32x4 xin) {
+    f32x4 d[4];
+    u32x4 h[2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        d[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a0[mt]), as_bf16x8(xin), net.b0[mt], 0, 0, 0);
+    activate(d, h);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a1[mt][0]), as_bf16x8(h[0]), net.b1[mt], 0, 0, 0);
+        d[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a1[mt][1]), as_bf16x8(h[1]), acc, 0, 0, 0);
+    }
+    activate(d, h);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a2[mt][0]), as_bf16x8(h[0]), net.b2[mt], 0, 0, 0);
+        d[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a2[mt][1]), as_bf16x8(h[1]), acc, 0, 0, 0);
+    }
+    activate(d, h);
+    f32x4 y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a3[0]), as_bf16x8(h[0]), net.b3, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a3[1]), as_bf16x8(h[1]), y, 0, 0, 0);
+}
+
+// Layer-0 B operand of lane group g from the six normalised FP32 inputs:
+// slots 0-5 hi, 6-11 lo, 12-17 hi, 18-31 zero (see the file comment).
+__device__ __forceinline__ u32x4 input_operand(const float (&xn)[6], int g) {
+    uint32_t hi[3], lo[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float h0 = bf16_round(xn[2 * q]), h1 = bf16_round(xn[2 * q + 1]);
+        hi[q] = pack_bf16x2(h0, h1);
+        lo[q] = pack_bf16x2(xn[2 * q] - h0, xn[2 * q + 1] - h1);
+    }
+    // g = 0: hi01 hi23 hi45 lo01 | g = 1: lo23 lo45 hi01 hi23 | g = 2: hi45 0 0 0 | g = 3: 0
+    const u32x4 v0 = {hi[0], hi[1], hi[2], lo[0]};
+    const u32x4 v1 = {lo[1], lo[2], hi[0], hi[1]};
+    const u32x4 v2 = {hi[2], 0u, 0u, 0u};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    return g == 0 ? v0 : g == 1 ? v1 : g == 2 ? v2 : zero;
+}
+
+constexpr int kInferBlock = 256;
+
+// Persistent grid; each wavefront takes groups of 64 particles: lane column n
+// (= l % 16) of N-tile t holds particle base + 4n + t, so a lane's four
+// particles are contiguous in every bunch row.
+__global__ __launch_bounds__(kInferBlock) void k_mlp_infer(double* __restrict__ z, int64_t n, int64_t ld,
+                                                           const uint32_t* __restrict__ img, NormArgs na) {
+    Net net;
+    load_net(img, net);
+    const int l = threadIdx.x & 63, col = l % 16, g = l / 16;
+    const int64_t waves = (int64_t)gridDim.x * (kInferBlock / 64);
+    const int64_t wave = (int64_t)blockIdx.x * (kInferBlock / 64) + (threadIdx.x >> 6);
+    for (int64_t base = wave * 64; base < n; base += waves * 64) {
+        const int64_t p0 = base + 4 * col;
+        const bool full = base + 64 <= n;
+        double x[4][6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double* row = z + j * ld;
+            if (full) {
+                const double2 a = *reinterpret_cast<const double2*>(row + p0);
+                const double2 b = *reinterpret_cast<const double2*>(row + p0 + 2);
+                x[0][j] = a.x; x[1][j] = a.y; x[2][j] = b.x; x[3][j] = b.y;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) x[t][j] = (p0 + t < n) ? row[p0 + t] : na.mu_in[j];
+            }
+        }
+        f32x4 y[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float xn[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) xn[j] = (float)((x[t][j] - na.mu_in[j]) * na.inv_sd_in[j]);
+            y[t] = forward_tile(net, input_operand(xn, g));
+        }
+        // lane group 0 holds output rows 0..3, group 1 rows 4..5
+        if (g < 2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 4 * g + i;
+                if (j < kIn) {
+                    double* row = z + j * ld;
+                    double o[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) o[t] = fma(na.sd_out[j], (double)y[t][i], na.mu_out[j]);
+                    if (full) {
+                        *reinterpret_cast<double2*>(row + p0) = double2{o[0], o[1]};
+                        *reinterpret_cast<double2*>(row + p0 + 2) = double2{o[2], o[3]};
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (p0 + t < n) row[p0 + t] = o[t];
+                    }
+                }
+            }
+        }
+    }
+}
+
+
+// ================================================================ training
+// One training step over a batch (§3: MSE of Eq. (4), Adam): k_train_step
+// computes each 64-sample block's loss and gradient partials, k_train_adam
+// sums the partials over blocks in a fixed order and updates the FP32 master
+// parameters and moments, k_mlp_pack rebuilds the bf16 operand image.
+//
+// Rounding points, beyond those of inference: the output error d = yhat - y
+// is FP32 and delta3 = d * 2/(B n_out); every error that enters a matrix-core
+// product (delta3, delta2, delta1) is rounded to bf16, accumulation is FP32;
+// delta_{l-1} = (W_l^T delta_l)(1 - h_l^2) is formed in FP32 from the bf16
+// activation h_l; bias gradients sum the FP32 errors; the first-layer weight
+// gradient sums FP32 delta0 times the FP32 network input on the vector ALU.
+
+constexpr int kTrainBlock = 256;       // 4 waves x 16 samples
+constexpr int kTrainSamples = 64;
+
+struct TrainArgs {
+    const double* zin;
+    const double* zout;
+    int64_t ld;
+    const int32_t* idx;      // this step's batch: sample indices
+    const uint32_t* img;
+    float* part;             // [blocks][kNParams]
+    float* loss_part;        // [blocks]
+    NormArgs na;
+    double inv_sd_out[6];
+    float dscale;            // 2 / (B * 6)
+};
+
+__device__ __forceinline__ float bf16_elem(const u32x4& v, int j) {
+    const uint32_t w = v[j >> 1];
+    return (j & 1) ? __uint_as_float(w & 0xffff0000u) : __uint_as_float(w << 16);
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(const u32x4& v, int j) {
+    const uint32_t w = v[j >> 1];
+    return (uint16_t)((j & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// sum over the 16 lanes (columns) of a lane group
+__device__ __forceinline__ float group16_sum(float v) {
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
+__device__ __forceinline__ u32x4 ld4g(const uint32_t* __restrict__ img, int w, int l) {
+    return u32x4{img[(w + 0) * 64 + l], img[(w + 1) * 64 + l], img[(w + 2) * 64 + l], img[(w + 3) * 64 + l]};
+}
+
+// e = W^T delta (delta as two packed K-chunks), transposed operands at word base
+__device__ __forceinline__ void backprop64(const uint32_t* __restrict__ img, int base, int l,
+                                           const u32x4 (&dop)[2], f32x4 (&e)[4]) {
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ld4g(img, base + 8 * mt, l)), as_bf16x8(dop[0]), z, 0, 0, 0);
+        e[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ld4g(img, base + 8 * mt + 4, l)), as_bf16x8(dop[1]), acc, 0, 0, 0);
+    }
+}
+
+// delta_prev = e (1 - h^2) on this lane's 16 (feature, sample) entries, h the
+// packed bf16 activation at the same positions.  Stores h (bf16) into sH and
+// delta_prev into sD (bf16) or sF (FP32) as [feature][sample], and the
+// per-wave bias-gradient sums into sDB[wave][feature].
+template <bool F32>
+__device__ __forceinline__ void back_activate(const f32x4 (&e)[4], const u32x4 (&h)[2], int g, int wv,
+                                              int s, uint16_t* sH, uint16_t* sD, float* sF, float* sDB,
+                                              u32x4 (&dop)[2]) {
+    f32x4 dl[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int c = mt >> 1, jb = (mt & 1) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float hv = bf16_elem(h[c], jb + i);
+            dl[mt][i] = e[mt][i] * (1.0f - hv * hv);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const f32x4 p = dl[2 * c], q = dl[2 * c + 1];
+        dop[c] = u32x4{pack_bf16x2(p[0], p[1]), pack_bf16x2(p[2], p[3]), pack_bf16x2(q[0], q[1]), pack_bf16x2(q[2], q[3])};
+    }
+    const int col = threadIdx.x & 15;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int c = mt >> 1, jb = (mt & 1) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = 16 * mt + 4 * g + i;
+            sH[f * 64 + s] = bf16_bits(h[c], jb + i);
+            if (F32) sF[f * 64 + s] = dl[mt][i];
+            else sD[f * 64 + s] = bf16_bits(dop[c], jb + i);
+            const float b = group16_sum(dl[mt][i]);
+            if (col == 0) sDB[wv * 64 + f] = b;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_train_step(TrainArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t sD3[16 * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t sH3[64 * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t sD2[64 * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t sH2[64 * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t sD1[64 * 64];
+    __shared__ __attribute__((aligned(16))) uint16_t sH1[64 * 64];
+    __shared__ float sF0[64 * 64];
+    __shared__ float sX[6 * 64];
+    __shared__ float sDB[4][4 * 64];     // [layer][wave * 64 + feature]
+    __shared__ float sLoss[4];
+
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, col = l % 16, g = l / 16;
+    const int s = 16 * wv + col;
+    const int64_t gi = a.idx[(int64_t)blockIdx.x * kTrainSamples + s];
+    float xn[6], yt[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        xn[j] = (float)((a.zin[j * a.ld + gi] - a.na.mu_in[j]) * a.na.inv_sd_in[j]);
+        yt[j] = (float)((a.zout[j * a.ld + gi] - a.na.mu_out[j]) * a.inv_sd_out[j]);
+    }
+    if (g == 0) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) sX[j * 64 + s] = xn[j];
+    }
+    // ---- forward, keeping the bf16 activations H1..H3
+    u32x4 H1[2], H2[2], H3[2];
+    f32x4 y;
+    {
+        Net net;
+        load_net(a.img, net);
+        f32x4 d[4];
+        const u32x4 xin = input_operand(xn, g);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            d[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a0[mt]), as_bf16x8(xin), net.b0[mt], 0, 0, 0);
+        activate(d, H1);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a1[mt][0]), as_bf16x8(H1[0]), net.b1[mt], 0, 0, 0);
+            d[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a1[mt][1]), as_bf16x8(H1[1]), acc, 0, 0, 0);
+        }
+        activate(d, H2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a2[mt][0]), as_bf16x8(H2[0]), net.b2[mt], 0, 0, 0);
+            d[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a2[mt][1]), as_bf16x8(H2[1]), acc, 0, 0, 0);
+        }
+        activate(d, H3);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a3[0]), as_bf16x8(H3[0]), net.b3, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(net.a3[1]), as_bf16x8(H3[1]), y, 0, 0, 0);
+    }
+    // ---- loss and output error; lane group g holds output rows 4g + i
+    float lsum = 0.0f;
+    f32x4 d3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = 4 * g + i;
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) t = (row == j) ? yt[j] : t;
+        const float dd = row < kIn ? y[i] - t : 0.0f;
+        lsum = fmaf(dd, dd, lsum);
+        d3[i] = dd * a.dscale;
+        sD3[row * 64 + s] = __builtin_bit_cast(unsigned short, (__bf16)d3[i]);
+        const float b = group16_sum(d3[i]);
+        if (col == 0 && row < kIn) sDB[3][wv * 64 + row] = b;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (l == 0) sLoss[wv] = lsum;
+    // ---- back-propagation (K slot 8g + i of the layer-3 error <-> row 4g + i)
+    {
+        f32x4 e[4];
+        u32x4 dop[2];
+        const u32x4 d3op = {pack_bf16x2(d3[0], d3[1]), pack_bf16x2(d3[2], d3[3]), 0u, 0u};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+            e[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ld4g(a.img, 140 + 4 * mt, l)), as_bf16x8(d3op), z, 0, 0, 0);
+        }
+        back_activate<false>(e, H3, g, wv, s, sH3, sD2, nullptr, sDB[2], dop);   // delta2
+        backprop64(a.img, 156, l, dop, e);
+        back_activate<false>(e, H2, g, wv, s, sH2, sD1, nullptr, sDB[1], dop);   // delta1
+        backprop64(a.img, 188, l, dop, e);
+        back_activate<true>(e, H1, g, wv, s, sH1, nullptr, sF0, sDB[0], dop);    // delta0 (FP32)
+    }
+    __syncthreads();
+    // ---- weight gradients of layers 1..3 on the matrix cores: dW = delta h^T
+    //      over the block's 64 samples (K), 36 16x16 tiles over 4 waves
+    float* part = a.part + (int64_t)blockIdx.x * kNParams;
+    for (int q = wv; q < 36; q += 4) {
+        const uint16_t *sD, *sH;
+        int mo, ni, off, nout;
+        if (q < 16) { sD = sD1; sH = sH1; mo = q >> 2; ni = q & 3; off = kOffW1; nout = kW; }
+        else if (q < 32) { sD = sD2; sH = sH2; mo = (q - 16) >> 2; ni = (q - 16) & 3; off = kOffW2; nout = kW; }
+        else { sD = sD3; sH = sH3; mo = 0; ni = q - 32; off = kOffW3; nout = kIn; }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+            const u32x4 av = *reinterpret_cast<const u32x4*>(sD + (16 * mo + col) * 64 + 32 * kc + 8 * g);
+            const u32x4 bv = *reinterpret_cast<const u32x4*>(sH + (16 * ni + col) * 64 + 32 * kc + 8 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 16 * mo + 4 * g + r;
+            if (o < nout) part[off + o * kW + 16 * ni + col] = acc[r];
+        }
+    }
+    // ---- first-layer weight gradient (FP32), biases, loss
+    for (int t = threadIdx.x; t < 64 * kIn; t += kTrainBlock) {
+        const int o = t / kIn, i = t % kIn;
+        float acc = 0.0f;
+        for (int q = 0; q < 64; ++q) acc = fmaf(sF0[o * 64 + q], sX[i * 64 + q], acc);
+        part[kOffW0 + o * kIn + i] = acc;
+    }
+    for (int t = threadIdx.x; t < 3 * 64 + kIn; t += kTrainBlock) {
+        const int layer = t / 64, f = t % 64;
+        const int off = layer == 0 ? kOffB0 : layer == 1 ? kOffB1 : layer == 2 ? kOffB2 : kOffB3;
+        float b = 0.0f;
+        for (int w = 0; w < 4; ++w) b += sDB[layer][w * 64 + f];
+        part[off + f] = b;
+    }
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
+}
+
+struct AdamArgs {
+    float* p;
+    float* m;
+    float* v;
+    const float* part;
+    int32_t nb;
+    const float* loss_part;
+    double* loss_acc;        // += this step's loss
+    double loss_scale;       // 1 / (B * 6)
+    float lr_c1;             // lr / (1 - beta1^t)
+    float inv_c2;            // 1 / (1 - beta2^t)
+    float b1, b2, eps;
+};
+
+// Adam (Kingma & Ba 2015), bias-corrected, FP32 master weights.
+__global__ __launch_bounds__(256) void k_train_adam(AdamArgs a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < kNParams) {
+        float g = 0.0f;
+        for (int b = 0; b < a.nb; ++b) g += a.part[(int64_t)b * kNParams + i];
+        const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+        const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+        a.m[i] = m;
+        a.v[i] = v;
+        a.p[i] = a.p[i] - a.lr_c1 * m / (sqrtf(v * a.inv_c2) + a.eps);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int b = 0; b < a.nb; ++b) sum += (double)a.loss_part[b];
+        *a.loss_acc += sum * a.loss_scale;
+    }
+}
+
+// Gradient of one batch only (no update): sums the block partials.
+__global__ __launch_bounds__(256) void k_grad_sum(const float* part, int nb, float* grad) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < kNParams) {
+        float g = 0.0f;
+        for (int b = 0; b < nb; ++b) g += part[(int64_t)b * kNParams + i];
+        grad[i] = g;
+    }
+}
+
+// MSE over pairs [i0, i0 + n) (test split), FP64 block partials.
+__global__ __launch_bounds__(kInferBlock) void k_mlp_eval_loss(const double* __restrict__ zin,
+                                                               const double* __restrict__ zout, int64_t ld,
+                                                               int64_t i0, int64_t n,
+                                                               const uint32_t* __restrict__ img, NormArgs na,
+                                                               double* __restrict__ part) {
+    __shared__ double sw[kInferBlock / 64];
+    Net net;
+    load_net(img, net);
+    const int l = threadIdx.x & 63, col = l % 16, g = l / 16;
+    const int64_t waves = (int64_t)gridDim.x * (kInferBlock / 64);
+    const int64_t wave = (int64_t)blockIdx.x * (kInferBlock / 64) + (threadIdx.x >> 6);
+    double acc = 0.0;
+    for (int64_t base = wave * 64; base < n; base += waves * 64) {
+        const int64_t p0 = base + 4 * col;
+        f32x4 y[4];
+        float tg[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bool live = p0 + t < n;
+            const int64_t gi = i0 + p0 + t;
+            float xn[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j)
+                xn[j] = live ? (float)((zin[j * ld + gi] - na.mu_in[j]) * na.inv_sd_in[j]) : 0.0f;
+            y[t] = forward_tile(net, input_operand(xn, g));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 4 * g + i;
+                tg[t][i] = (live && row < kIn) ? (float)((zout[row * ld + gi] - na.mu_out[row]) / na.sd_out[row]) : 0.0f;
+            }
+        }
+        float lsum = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = (p0 + t < n) && (4 * g + i < kIn);
+                const float dd = ok ? y[t][i] - tg[t][i] : 0.0f;
+                lsum = fmaf(dd, dd, lsum);
+            }
+        acc += (double)lsum;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (l == 0) sw[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < kInferBlock / 64; ++w) sum += sw[w];
+        part[blockIdx.x] = sum;
+    }
+}
+
+__global__ void k_sum_scaled(const double* part, int nb, double scale, double* out) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[b];
+        *out = s * scale;
+    }
+}
+
+}  // namespace
+
+int mlp_nparams() { return kNParams; }
+int mlp_image_words() { return kImgWords * 64; }
+
+hipError_t launch_mlp_pack(const float* params, uint32_t* img, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, s, params, img);
+    return hipGetLastError();
+}
+
+static NormArgs make_norm(const double* norm24) {
+    NormArgs na;
+    for (int j = 0; j < 6; ++j) {
+        na.mu_in[j] = norm24[j];
+        na.inv_sd_in[j] = 1.0 / norm24[6 + j];
+        na.mu_out[j] = norm24[12 + j];
+        na.sd_out[j] = norm24[18 + j];
+    }
+    return na;
+}
+
+hipError_t launch_train_step(const double* zin, const double* zout, int64_t ld, const int32_t* idx,
+                             int32_t batch, const uint32_t* img, float* part, float* loss_part,
+                             const double* norm24, hipStream_t s) {
+    TrainArgs a;
+    a.zin = zin;
+    a.zout = zout;
+    a.ld = ld;
+    a.idx = idx;
+    a.img = img;
+    a.part = part;
+    a.loss_part = loss_part;
+    a.na = make_norm(norm24);
+    for (int j = 0; j < 6; ++j) a.inv_sd_out[j] = 1.0 / norm24[18 + j];
+    a.dscale = (float)(2.0 / ((double)batch * kIn));
+    hipLaunchKernelGGL(k_train_step, dim3(batch / kTrainSamples), dim3(kTrainBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_adam(float* p, float* m, float* v, const float* part, int32_t nb,
+                             const float* loss_part, double* loss_acc, double loss_scale, int64_t t,
+                             float lr, float b1, float b2, float eps, hipStream_t s) {
+    AdamArgs a;
+    a.p = p;
+    a.m = m;
+    a.v = v;
+    a.part = part;
+    a.nb = nb;
+    a.loss_part = loss_part;
+    a.loss_acc = loss_acc;
+    a.loss_scale = loss_scale;
+    const double c1 = 1.0 - pow((double)b1, (double)t), c2 = 1.0 - pow((double)b2, (double)t);
+    a.lr_c1 = (float)((double)lr / c1);
+    a.inv_c2 = (float)(1.0 / c2);
+    a.b1 = b1;
+    a.b2 = b2;
+    a.eps = eps;
+    hipLaunchKernelGGL(k_train_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_sum(const float* part, int32_t nb, float* grad, hipStream_t s) {
+    hipLaunchKernelGGL(k_grad_sum, dim3((kNParams + 255) / 256), dim3(256), 0, s, part, nb, grad);
+    return hipGetLastError();
+}
+
+int eval_loss_blocks(int64_t n) {
+    int64_t groups = (n + 63) / 64;
+    int64_t blocks = (groups + 3) / 4;
+    if (blocks > 512) blocks = 512;
+    if (blocks < 1) blocks = 1;
+    return (int)blocks;
+}
+
+hipError_t launch_eval_loss(const double* zin, const double* zout, int64_t ld, int64_t i0, int64_t n,
+                            const uint32_t* img, const double* norm24, double* part, double* out,
+                            hipStream_t s) {
+    const int nb = eval_loss_blocks(n);
+    hipLaunchKernelGGL(k_mlp_eval_loss, dim3(nb), dim3(kInferBlock), 0, s, zin, zout, ld, i0, n, img,
+                       make_norm(norm24), part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_scaled, dim3(1), dim3(64), 0, s, part, nb, 1.0 / ((double)n * kIn), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* img, const double* norm24,
+                            hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const NormArgs na = make_norm(norm24);
+    int64_t groups = (n + 63) / 64;
+    int64_t blocks = (groups + 3) / 4;
+    const int64_t cap = 256 * 2;  // persistent: two 4-wave blocks per CU
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na);
+    return hipGetLastError();
+}
+
+}  // namespace hbl

@@ -46,6 +46,16 @@ class Ref(C.Structure):
         return Ref(self.mass_MeV, self.gamma, self.s)
 
 
+class MlpShape(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("hidden", C.c_int32), ("n_out", C.c_int32)]
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("max_steps", C.c_int64), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("train_frac", C.c_double),
+                ("shuffle_seed", C.c_uint64)]
+
+
 def _load():
     # torch's HIP runtime must be the one libhbl binds to: import torch first,
     # so that libhbl's libamdhip64.so.7 dependency resolves (by soname) to the
@@ -69,6 +79,20 @@ def _load():
         "hbl_moments_async": ([vp, i64, i64, vp, vp], st),
         "hbl_emittances": ([dp, dp], st),
         "hbl_compare": ([vp, vp, i64, i64, dp, dp, dp, vp], st),
+        "hbl_surrogate_create": ([C.POINTER(MlpShape), C.c_uint64, C.POINTER(vp)], st),
+        "hbl_surrogate_destroy": ([vp], st),
+        "hbl_surrogate_num_params": ([vp, C.POINTER(i64)], st),
+        "hbl_surrogate_get_params": ([vp, C.POINTER(C.c_float), i64], st),
+        "hbl_surrogate_set_params": ([vp, C.POINTER(C.c_float), i64], st),
+        "hbl_surrogate_get_norm": ([vp, dp], st),
+        "hbl_surrogate_set_norm": ([vp, dp], st),
+        "hbl_surrogate_set_stage": ([vp, C.POINTER(Element), C.POINTER(Ref)], st),
+        "hbl_surrogate_train": ([vp, vp, vp, i64, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp], st),
+        "hbl_surrogate_loss_grad": ([vp, vp, vp, i64, C.POINTER(C.c_int32), i32, C.POINTER(C.c_float),
+                                     dp, vp], st),
+        "hbl_surrogate_apply": ([vp, i64, i64, vp, C.POINTER(Ref), vp], st),
+        "hbl_surrogate_save": ([vp, C.c_char_p], st),
+        "hbl_surrogate_load": ([C.c_char_p, C.POINTER(vp)], st),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -203,3 +227,89 @@ def compare(zs, zf, n=None, stream=None):
     r, c, e = (C.c_double * 6)(), (C.c_double * 6)(), (C.c_double * 3)()
     _call("hbl_compare", ps, pf, n, ld, r, c, e, stream or current_stream())
     return list(r), list(c), list(e)
+
+
+class Surrogate:
+    """Neural-network stage surrogate (tanh MLP 6-64-64-64-6) owned by libhbl."""
+
+    def __init__(self, seed: int = 0, _handle=None):
+        if _handle is None:
+            h = C.c_void_p()
+            _call("hbl_surrogate_create", C.byref(MlpShape(6, 64, 3, 6)), seed, C.byref(h))
+            _handle = h
+        self._h = _handle
+        n = C.c_int64()
+        _call("hbl_surrogate_num_params", self._h, C.byref(n))
+        self.n_params = n.value
+
+    @staticmethod
+    def load(path: str) -> "Surrogate":
+        h = C.c_void_p()
+        _call("hbl_surrogate_load", path.encode(), C.byref(h))
+        return Surrogate(_handle=h)
+
+    def save(self, path: str):
+        _call("hbl_surrogate_save", self._h, path.encode())
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        _call("hbl_surrogate_get_params", self._h, out.ctypes.data_as(C.POINTER(C.c_float)), self.n_params)
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _call("hbl_surrogate_set_params", self._h, p.ctypes.data_as(C.POINTER(C.c_float)), len(p))
+
+    def get_norm(self):
+        out = (C.c_double * 24)()
+        _call("hbl_surrogate_get_norm", self._h, out)
+        return list(out)
+
+    def set_norm(self, norm):
+        _call("hbl_surrogate_set_norm", self._h, (C.c_double * 24)(*norm))
+
+    def set_stage(self, stage, ref_at_entry: Ref):
+        el = stage if isinstance(stage, Element) else element(stage)
+        _call("hbl_surrogate_set_stage", self._h, C.byref(el), C.byref(ref_at_entry))
+
+    def train(self, zin, zout, n_pairs, batch=4096, epochs=1, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              train_frac=0.7, shuffle_seed=0, max_steps=-1, stream=None):
+        import numpy as np
+        pin, _, ld = _bunch_args(zin, n_pairs)
+        pout, _, ldo = _bunch_args(zout, n_pairs)
+        if ldo != ld:
+            raise ValueError("train: input and output pairs need the same leading dimension")
+        cfg = TrainCfg(batch, epochs, max_steps, lr, beta1, beta2, eps, train_frac, shuffle_seed)
+        log = np.zeros(2 * max(epochs, 1), dtype=np.float32)
+        _call("hbl_surrogate_train", self._h, pin, pout, n_pairs, ld, C.byref(cfg),
+              log.ctypes.data_as(C.POINTER(C.c_float)), stream or current_stream())
+        return log[: 2 * epochs].reshape(epochs, 2)
+
+    def loss_grad(self, zin, zout, idx, stream=None):
+        import numpy as np
+        pin, _, ld = _bunch_args(zin)
+        pout, _, _ = _bunch_args(zout)
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        _call("hbl_surrogate_loss_grad", self._h, pin, pout, ld, idx.ctypes.data_as(C.POINTER(C.c_int32)),
+              len(idx), g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), stream or current_stream())
+        return loss.value, g
+
+    def apply(self, z, ref: Optional[Ref] = None, n=None, stream=None):
+        ptr, n, ld = _bunch_args(z, n)
+        _call("hbl_surrogate_apply", ptr, n, ld, self._h, C.byref(ref) if ref is not None else None,
+              stream or current_stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.hbl_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,210 @@
+"""GPU parity of the surrogate network (§3 Eq. 3-4, Adam) against the CPU
+oracle's bf16-emulation mode, through the C ABI.
+
+Expected differences (the oracle accumulates in FP64 and evaluates tanh
+exactly; the GPU accumulates in FP32 on the matrix cores and evaluates tanh
+from exp2/reciprocal approximations, ~1e-7 relative): a value that lands
+within ~1e-7 of a bf16 rounding boundary rounds the other way, a one-ulp
+(2^-8 relative) change of one activation in ~1e-4 of all activations.  Most
+outputs therefore agree to ~1e-6 (normalised units) and a few percent of the
+particles move by up to ~1e-2."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hbl():
+    from paper_2402_17248_amd import hbl as h
+    return h
+
+
+@pytest.fixture(scope="module")
+def pairs(hbl):
+    """2^14 stage pairs: triplet, then the fine-step stage with its input recorded."""
+    n = 1 << 14
+    wl = W.c3_stage(n=n, nsub=400)
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, 3, (0.0,) * 6, wl.bunch.sigma, n=n)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
+    rec = hbl.new_bunch(n)
+    entry = ref.copy()
+    hbl.apply_stage(z, wl.beamline[1], ref, record=rec, n=n)
+    return n, rec, z, to_host(rec, n), to_host(z, n), wl.beamline[1], entry
+
+
+def perturbed(orc, seed):
+    p = orc.mlp_init(orc.shape(), seed)
+    rng = np.random.default_rng(seed)
+    return (p + 0.05 * rng.standard_normal(p.shape)).astype(np.float32)
+
+
+def test_init_matches_oracle(hbl, orc):
+    for seed in (0, 101, 2**40 + 3):
+        s = hbl.Surrogate(seed)
+        assert np.array_equal(s.get_params(), orc.mlp_init(orc.shape(), seed))
+
+
+def test_forward_parity(hbl, orc, pairs):
+    n, rec, out, xin, xout, _, _ = pairs
+    norm = orc.norm_stats(xin, xout, n)
+    s = hbl.Surrogate(0)
+    p = perturbed(orc, 5)
+    s.set_params(p)
+    s.set_norm(norm)
+    m = 10_001
+    z = rec[:, :m + 1].clone()
+    s.apply(z, n=m)
+    g = to_host(z, m)
+    c = orc.mlp_apply(orc.shape(), p, norm, np.ascontiguousarray(xin[:, :m]), mode=1)
+    d = np.abs(g - c) / norm[18:24, None]
+    frac_off = np.mean(d.max(axis=0) > 1e-4)
+    assert d.max() < 5e-2, d.max()
+    assert frac_off < 0.05, frac_off
+    assert np.median(d) < 1e-6
+
+
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 130])
+def test_forward_ragged_sizes(hbl, orc, pairs, m):
+    n, rec, out, xin, xout, _, _ = pairs
+    norm = orc.norm_stats(xin, xout, n)
+    s = hbl.Surrogate(0)
+    p = perturbed(orc, 6)
+    s.set_params(p)
+    s.set_norm(norm)
+    z = rec.clone()
+    s.apply(z, n=m)
+    g = to_host(z, n)
+    c = orc.mlp_apply(orc.shape(), p, norm, np.ascontiguousarray(xin[:, :m]), mode=1)
+    d = np.abs(g[:, :m] - c) / norm[18:24, None]
+    assert d.max() < 5e-2
+    assert np.array_equal(g[:, m:], xin[:, m:])          # particles past n untouched
+
+
+def test_forward_full_size_sampled(hbl, orc, pairs):
+    n, rec, out, xin, xout, _, _ = pairs
+    norm = orc.norm_stats(xin, xout, n)
+    s = hbl.Surrogate(0)
+    p = perturbed(orc, 7)
+    s.set_params(p)
+    s.set_norm(norm)
+    N = W.C4_INFER_N
+    z = hbl.new_bunch(N)
+    hbl.fill_gaussian(z, W.C4_INFER_SEED, tuple(norm[0:6]), tuple(norm[6:12]), n=N)
+    torch = __import__("torch")
+    idx = np.sort(np.random.default_rng(3).choice(N, 2000, replace=False))
+    idx[-1] = N - 1
+    ti = torch.from_numpy(idx).cuda()
+    x0 = np.ascontiguousarray(z[:, ti].cpu().numpy())
+    s.apply(z, n=N)
+    g = np.ascontiguousarray(z[:, ti].cpu().numpy())
+    c = orc.mlp_apply(orc.shape(), p, norm, x0, mode=1)
+    d = np.abs(g - c) / norm[18:24, None]
+    assert d.max() < 5e-2 and np.mean(d.max(axis=0) > 1e-4) < 0.05
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+TENSORS = [("W0", 0, 384), ("b0", 384, 448), ("W1", 448, 4544), ("b1", 4544, 4608), ("W2", 4608, 8704),
+           ("b2", 8704, 8768), ("W3", 8768, 9152), ("b3", 9152, 9158)]
+
+
+def test_gradient_parity(hbl, orc, pairs):
+    n, rec, out, xin, xout, _, _ = pairs
+    norm = orc.norm_stats(xin, xout, n)
+    s = hbl.Surrogate(0)
+    p = perturbed(orc, 8)
+    s.set_params(p)
+    s.set_norm(norm)
+    idx = np.random.default_rng(4).choice(n, 512, replace=False).astype(np.int32)
+    loss_g, g = s.loss_grad(rec, out, idx)
+    loss_o, go = orc.mlp_loss_grad(orc.shape(), p, norm, xin, xout, idx.astype(np.int64), mode=1)
+    assert abs(loss_g / loss_o - 1) < 1e-5
+    for name, a, b in TENSORS:
+        assert rel_fro(g[a:b].astype(np.float64), go[a:b]) < 1e-2, name
+    # and against the exact FP64 gradient (the bf16 rounding points move it by ~1e-2)
+    _, g64 = orc.mlp_loss_grad(orc.shape(), p, norm, xin, xout, idx.astype(np.int64), mode=0)
+    assert rel_fro(g.astype(np.float64), g64) < 5e-2
+
+
+def test_first_adam_step_and_epoch_order(hbl, orc, pairs):
+    """One optimizer step of training equals the oracle's Adam applied to the
+    gradient of the first batch of the oracle's epoch-0 Fisher-Yates order."""
+    n, rec, out, xin, xout, _, _ = pairs
+    s = hbl.Surrogate(11)
+    p0 = s.get_params()
+    s.train(rec, out, n, batch=64, epochs=1, lr=1e-3, train_frac=0.7, shuffle_seed=77, max_steps=1)
+    p1 = s.get_params()
+    ntr = int(round(0.7 * n))
+    first = orc.epoch_perm(ntr, 77, 0)[:64].astype(np.int32)
+    ref = hbl.Surrogate(11)
+    ref.set_norm(s.get_norm())
+    _, g = ref.loss_grad(rec, out, first)
+    want, _, _ = orc.adam_step(p0, np.zeros(len(p0)), np.zeros(len(p0)), g.astype(np.float64), 1, lr=1e-3)
+    assert np.abs(p1 - want).max() < 1e-6
+    # the training normalisation is the oracle's over the training split
+    on = orc.norm_stats(xin, xout, ntr)
+    assert np.allclose(s.get_norm(), on, rtol=1e-13, atol=0)
+
+
+def test_training_curve_matches_oracle(hbl, orc, pairs):
+    n, rec, out, xin, xout, _, _ = pairs
+    s = hbl.Surrogate(12)
+    p0 = s.get_params()
+    log = s.train(rec, out, n, batch=256, epochs=3, lr=3e-3, shuffle_seed=5)
+    _, _, olog = orc.mlp_train(orc.shape(), p0, xin, xout, batch=256, epochs=3, lr=3e-3, shuffle_seed=5, mode=1)
+    assert np.all(np.isfinite(log))
+    assert log[-1, 1] < 0.7 * log[0, 1]
+    assert np.all(np.abs(log / olog - 1) < 0.1), (log, olog)
+
+
+def test_save_load_roundtrip(hbl, orc, pairs):
+    n, rec, out, xin, xout, stage, entry = pairs
+    s = hbl.Surrogate(3)
+    s.train(rec, out, n, batch=256, epochs=1, lr=1e-3, shuffle_seed=1)
+    s.set_stage(stage, entry)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.hbls")
+        s.save(path)
+        t = hbl.Surrogate.load(path)
+        assert np.array_equal(s.get_params(), t.get_params())
+        assert s.get_norm() == t.get_norm()
+        z1, z2 = rec.clone(), rec.clone()
+        r1, r2 = entry.copy(), entry.copy()
+        s.apply(z1, r1, n=n)
+        t.apply(z2, r2, n=n)
+        __import__("torch").cuda.synchronize()
+        assert __import__("torch").equal(z1, z2)
+        assert (r1.gamma, r1.s) == (r2.gamma, r2.s)
+        with open(path, "r+b") as fh:
+            fh.seek(200)
+            b = fh.read(1)
+            fh.seek(200)
+            fh.write(bytes([b[0] ^ 1]))
+        with pytest.raises(hbl.HblError) as ei:
+            hbl.Surrogate.load(path)
+        assert ei.value.status == hbl.HBL_EIO
+
+
+def test_apply_moves_reference_and_checks_entry(hbl, orc, pairs):
+    n, rec, out, xin, xout, stage, entry = pairs
+    s = hbl.Surrogate(0)
+    s.set_norm(orc.norm_stats(xin, xout, n))
+    s.set_stage(stage, entry)
+    r = entry.copy()
+    s.apply(rec.clone(), r, n=n)
+    assert abs(r.gamma - (entry.gamma + stage.dE_MeV / hbl.MEC2_MEV)) < 1e-9 and abs(r.s - entry.s - stage.L) < 1e-15
+    bad = hbl.Ref.from_energy(2000.0)
+    with pytest.raises(hbl.HblError) as ei:
+        s.apply(rec.clone(), bad, n=n)
+    assert ei.value.status == hbl.HBL_EINVAL
