@@ -177,7 +177,10 @@ typedef struct hbl_mlp_shape {
 } hbl_mlp_shape;
 
 /* Training recipe.  batch: multiple of 64; epochs >= 0; max_steps < 0 = no
- * limit, else training stops after that many optimizer steps; the first
+ * limit, else training stops after that many optimizer steps.  Learning
+ * rate: lr at the first step, annealed by a half cosine to lr_final at the
+ * last of the T planned steps, lr_t = lr_final + (lr - lr_final)(1 +
+ * cos(pi (t-1)/(T-1)))/2 (constant when lr_final == lr).  The first
  * round(train_frac * n_pairs) pairs train, the rest test (§3: 70/30); each
  * epoch visits the training pairs in a Fisher-Yates order (Philox4x32-10,
  * key shuffle_seed, counter (i/4, epoch, 'SHUF'), word i%4, j = floor(r (i+1)
@@ -186,7 +189,7 @@ typedef struct hbl_train_cfg {
     int32_t batch;
     int32_t epochs;
     int64_t max_steps;
-    float lr, beta1, beta2, eps;
+    float lr, lr_final, beta1, beta2, eps;
     double train_frac;
     uint64_t shuffle_seed;
 } hbl_train_cfg;

@@ -441,9 +441,12 @@ int orc_mlp_init(const orc_shape* sh, uint64_t seed, float* params)
 /* Forward pass of one sample.  xin: raw input (6 doubles).  Stores the
  * network input actually used (act[0]), each hidden activation act[l] and the
  * normalised output yhat.  Mode 1 applies the GPU rounding points:
- *   input: FP32 value split into bf16 hi + lo, first-layer weights split the
- *   same way, product keeps hi*hi + hi*lo + lo*hi; hidden weights and
- *   activations bf16; tanh of the FP32 pre-activation; output FP32. */
+ *   hidden layers form the pre-activation scaled by c = 2/ln 2 (FP32 c),
+ *   from FP32 c*w and c*b, and take tanh(ln2/2 * that);
+ *   input: FP32 value split into bf16 hi + lo, first-layer (scaled) weights
+ *   split the same way, product keeps hi*hi + hi*lo + lo*hi; other hidden
+ *   weights and activations bf16; output layer unscaled, result FP32. */
+#define ORC_TANH_SCALE 2.8853900817779268f
 typedef struct { double act[8][MAXW]; double yhat[MAXW]; } fwd_state;
 
 static void forward_one(const orc_shape* sh, const float* prm, const double* norm, int mode,
@@ -460,8 +463,9 @@ static void forward_one(const orc_shape* sh, const float* prm, const double* nor
         const float* b = A + (int64_t)no * ni;
         const double* in = st->act[l];
         double* out = (l == H) ? st->yhat : st->act[l + 1];
+        const float cs = (mode && l < H) ? ORC_TANH_SCALE : 1.0f;
         for (int o = 0; o < no; o++) {
-            double acc = (double)b[o];
+            double acc = mode ? (double)(b[o] * cs) : (double)b[o];
             for (int i = 0; i < ni; i++) {
                 float w = A[(int64_t)o * ni + i];
                 if (!mode) {
@@ -469,10 +473,11 @@ static void forward_one(const orc_shape* sh, const float* prm, const double* nor
                 } else if (l == 0) {
                     float xs = (float)in[i];
                     float xhi = orc_bf16(xs), xlo = orc_bf16(xs - xhi);
-                    float whi = orc_bf16(w), wlo = orc_bf16(w - whi);
+                    float wc = w * cs;
+                    float whi = orc_bf16(wc), wlo = orc_bf16(wc - whi);
                     acc += (double)whi * xhi + (double)whi * xlo + (double)wlo * xhi;
                 } else {
-                    acc += (double)orc_bf16(w) * in[i];
+                    acc += (double)orc_bf16(w * cs) * in[i];
                 }
             }
             if (l == H) {
@@ -480,7 +485,7 @@ static void forward_one(const orc_shape* sh, const float* prm, const double* nor
             } else if (!mode) {
                 out[o] = tanh(acc);
             } else {
-                out[o] = (double)orc_bf16((float)tanh((double)(float)acc));
+                out[o] = (double)orc_bf16((float)tanh((double)(float)acc * (0.5 * M_LN2)));
             }
         }
     }
@@ -614,8 +619,8 @@ int orc_epoch_perm(int64_t n, uint64_t seed, int64_t epoch, int64_t* perm)
 
 int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
                   const double* zin, const double* zout, int64_t n_pairs, int64_t ld,
-                  int64_t batch, int64_t epochs, int64_t max_steps, double lr, double b1,
-                  double b2, double eps, double train_frac, uint64_t shuffle_seed,
+                  int64_t batch, int64_t epochs, int64_t max_steps, double lr, double lr_final,
+                  double b1, double b2, double eps, double train_frac, uint64_t shuffle_seed,
                   double* loss_log)
 {
     const int64_t n_train = (int64_t)llround(train_frac * (double)n_pairs);
@@ -630,6 +635,9 @@ int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
     int64_t* tidx = (int64_t*)malloc((n_test > 0 ? n_test : 1) * sizeof(int64_t));
     for (int64_t i = 0; i < n_test; i++) tidx[i] = n_train + i;
     const int64_t steps_per_epoch = n_train / batch;
+    /* learning rate: half-cosine anneal from lr to lr_final over the planned steps */
+    int64_t planned = epochs * steps_per_epoch;
+    if (max_steps >= 0 && max_steps < planned) planned = max_steps;
     int64_t t = 0;
     for (int64_t e = 0; e < epochs; e++) {
         orc_epoch_perm(n_train, shuffle_seed, e, perm);
@@ -640,7 +648,10 @@ int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
             double loss;
             orc_mlp_loss_grad(sh, params, norm, mode, zin, zout, ld, perm + s * batch, batch, g, &loss);
             t++;
-            orc_adam_step(np, params, m, v, g, t, lr, b1, b2, eps);
+            double lr_t = lr;
+            if (planned > 1 && lr_final != lr)
+                lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + cos(M_PI * (double)(t - 1) / (double)(planned - 1)));
+            orc_adam_step(np, params, m, v, g, t, lr_t, b1, b2, eps);
             lsum += loss;
             done++;
         }

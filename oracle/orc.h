@@ -83,8 +83,8 @@ int orc_epoch_perm(int64_t n, uint64_t seed, int64_t epoch, int64_t* perm);
 /* Full training loop; loss_log[2*e] = mean train loss, [2*e+1] = test loss. */
 int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
                   const double* zin, const double* zout, int64_t n_pairs, int64_t ld,
-                  int64_t batch, int64_t epochs, int64_t max_steps, double lr, double b1,
-                  double b2, double eps, double train_frac, uint64_t shuffle_seed,
+                  int64_t batch, int64_t epochs, int64_t max_steps, double lr, double lr_final,
+                  double b1, double b2, double eps, double train_frac, uint64_t shuffle_seed,
                   double* loss_log);
 
 #ifdef __cplusplus

@@ -74,7 +74,7 @@ def lib():
         L.orc_norm_stats.argtypes = [dp, dp, i64, i64, dp]
         L.orc_epoch_perm.argtypes = [i64, C.c_uint64, i64, C.POINTER(C.c_int64)]
         L.orc_mlp_train.argtypes = [C.POINTER(_Shape), fp, dp, C.c_int, dp, dp, i64, i64, i64, i64,
-                                    i64, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    i64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_uint64, dp]
         _lib = L
     return _lib
@@ -258,12 +258,13 @@ def epoch_perm(n, seed, epoch):
 
 
 def mlp_train(sh, params, zin, zout, batch, epochs, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8,
-              train_frac=0.7, shuffle_seed=0, mode=1, max_steps=-1):
+              train_frac=0.7, shuffle_seed=0, mode=1, max_steps=-1, lr_final=None):
     zin, zout = _bunch(zin), _bunch(zout)
     params = np.ascontiguousarray(params, dtype=np.float32).copy()
     norm = np.empty(24)
     log = np.zeros(2 * epochs)
     _check(lib().orc_mlp_train(C.byref(sh), _fp(params), _dp(norm), mode, _dp(zin), _dp(zout),
-                               zin.shape[1], zin.shape[1], batch, epochs, max_steps, lr, b1, b2, eps,
+                               zin.shape[1], zin.shape[1], batch, epochs, max_steps, lr,
+                               lr if lr_final is None else lr_final, b1, b2, eps,
                                train_frac, shuffle_seed, _dp(log)), "train")
     return params, norm, log.reshape(epochs, 2)

@@ -31,6 +31,53 @@ class Chain:
         """Particle-element pushes per particle (a stage counts as one)."""
         return sum(v.n_elem if k == "lattice" else 1 for k, v in self.segments)
 
+    def entry_ref(self, k: int) -> hbl.Ref:
+        """Reference particle at the entrance of stage k (0-based)."""
+        ref = hbl.Ref.from_energy(self.E_MeV)
+        j = 0
+        for kind, v in self.segments:
+            if kind == "lattice":
+                ref.s += v.length
+                continue
+            if j == k:
+                return ref
+            ref.gamma += v.dE_MeV / ref.mass_MeV
+            ref.s += v.L
+            j += 1
+        raise IndexError(k)
+
+    def stage(self, k: int) -> hbl.Element:
+        return [v for kind, v in self.segments if kind == "stage"][k]
+
+    def make_pairs(self, k: int, n_pairs: int, seed: int, sigma, stream=None):
+        """Training pairs for stage k (§3, §4.1): a fresh Gaussian bunch tracked
+        with fine-step stages to the entrance of stage k, then stage k with its
+        input recorded.  Returns (inputs, outputs) device bunches."""
+        zin = hbl.new_bunch(n_pairs)
+        zout = hbl.new_bunch(n_pairs)
+        hbl.fill_gaussian(zout, seed, (0.0,) * 6, sigma, n=n_pairs, stream=stream)
+        self.run(zout, n=n_pairs, stop_before_stage=k, record=zin, stream=stream)
+        return zin, zout
+
+    def train_surrogates(self, n_pairs: int, sigma, pair_seed, init_seed, shuffle_seed, epochs: int,
+                         batch=4096, lr=1e-3, lr_final=1e-5, train_frac=0.7, stages=None, log=None):
+        """Train one surrogate per stage, each on its own pairs (the paper
+        trains one network per stage, §4.2).  Seeds are callables of the
+        1-based stage number."""
+        logs = []
+        for k in (range(self.stage_count) if stages is None else stages):
+            zin, zout = self.make_pairs(k, n_pairs, pair_seed(k + 1), sigma)
+            sur = hbl.Surrogate(init_seed(k + 1))
+            curve = sur.train(zin, zout, n_pairs, batch=batch, epochs=epochs, lr=lr, lr_final=lr_final,
+                              train_frac=train_frac, shuffle_seed=shuffle_seed(k + 1))
+            sur.set_stage(self.stage(k), self.entry_ref(k))
+            self.surrogates[k] = sur
+            logs.append(curve)
+            if log:
+                log(f"stage {k + 1}: trained {epochs} epochs, final (train, test) loss {curve[-1].tolist()}")
+            del zin, zout
+        return logs
+
     def run(self, z, n=None, use_surrogates=False, stop_before_stage: Optional[int] = None,
             record=None, fused=True, stream=None) -> hbl.Ref:
         """Push z in place.  stop_before_stage=k stops at the entrance of stage k

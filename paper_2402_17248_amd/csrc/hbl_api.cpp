@@ -863,6 +863,7 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
                 "surrogate_train: batch %d must be a positive multiple of 64", cfg->batch);
     HBL_REQUIRE(cfg->epochs >= 0 && cfg->epochs <= 1000000, "surrogate_train: bad epoch count");
     HBL_REQUIRE(isfinite(cfg->lr) && cfg->lr > 0, "surrogate_train: lr must be > 0");
+    HBL_REQUIRE(isfinite(cfg->lr_final) && cfg->lr_final > 0, "surrogate_train: lr_final must be > 0");
     HBL_REQUIRE(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1, "surrogate_train: betas must be in [0,1)");
     HBL_REQUIRE(isfinite(cfg->eps) && cfg->eps > 0, "surrogate_train: eps must be > 0");
     HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "surrogate_train: train_frac must be in (0, 1]");
@@ -914,6 +915,13 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
         if (e != hipSuccess) fail(HBL_ENOMEM, "order buffers", e);
     }
     std::vector<int64_t> steps_done(cfg->epochs > 0 ? cfg->epochs : 1, 0);
+    int64_t planned = (int64_t)cfg->epochs * steps_per_epoch;
+    if (cfg->max_steps >= 0 && cfg->max_steps < planned) planned = cfg->max_steps;
+    auto lr_at = [&](int64_t t) {  // t = 1..planned, half-cosine anneal
+        if (planned <= 1 || cfg->lr_final == cfg->lr) return (double)cfg->lr;
+        const double ph = 3.14159265358979323846 * (double)(t - 1) / (double)(planned - 1);
+        return (double)cfg->lr_final + 0.5 * ((double)cfg->lr - (double)cfg->lr_final) * (1.0 + cos(ph));
+    };
     for (int64_t ep = 0; ep < cfg->epochs && st == HBL_OK; ++ep) {
         const int k = (int)(ep & 1);
         hipError_t e = hipEventSynchronize(ev[k]);   // the copy two epochs ago has finished
@@ -930,7 +938,7 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
             if (e == hipSuccess)
                 e = launch_train_adam(m->d_params, m->d_m, m->d_v, m->d_part, nb, m->d_loss_part,
                                       m->d_loss_acc + 2 * ep, 1.0 / ((double)cfg->batch * 6.0), m->step,
-                                      cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, s);
+                                      (float)lr_at(m->step), cfg->beta1, cfg->beta2, cfg->eps, s);
             if (e == hipSuccess) e = launch_mlp_pack(m->d_params, m->d_img, s);
             if (e != hipSuccess) { fail(HBL_EHIP, "step launch", e); break; }
             steps_done[ep] += 1;

@@ -48,10 +48,14 @@ __device__ __forceinline__ float bf16_round(float a) {
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-// tanh(a) = 1 - 2 / (2^(2 a log2 e) + 1): one exp2, one reciprocal (both
-// hardware approximations, ~1 ulp), saturating correctly for large |a|.
-__device__ __forceinline__ float tanh_f32(float a) {
-    const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);
+// Hidden-layer pre-activations are computed pre-scaled by c = 2/ln 2: the
+// forward weight image holds bf16(c W) and c b (see k_mlp_pack), so that
+// tanh(a) = 1 - 2 / (2^(c a) + 1) needs one exp2 and one reciprocal (both
+// hardware approximations, ~1 ulp) and no multiply; it saturates correctly
+// for large |a|.
+constexpr float kTanhScale = 2.8853900817779268f;  // 2 / ln 2
+__device__ __forceinline__ float tanh_scaled(float ca) {
+    const float e = __builtin_amdgcn_exp2f(ca);
     const float r = __builtin_amdgcn_rcpf(e + 1.0f);
     return fmaf(-2.0f, r, 1.0f);
 }
@@ -67,6 +71,7 @@ __host__ __device__ __forceinline__ int perm_feature(int c, int g, int j) {
 //   words  16.. 47  layer 1 A operands, (mt, c): 16 + 8mt + 4c
 //   words  48.. 79  layer 2 A operands, (mt, c): 48 + 8mt + 4c
 //   words  80.. 87  layer 3 A operands, c: 80 + 4c
+//   (layers 0..2 hold bf16(c W) and, below, c b with c = 2/ln 2)
 //   words  88..103  layer 0 bias, M-tile mt rows 16mt + 4g + i: 88 + 4mt + i
 //   words 104..119  layer 1 bias
 //   words 120..135  layer 2 bias
@@ -88,6 +93,8 @@ __global__ void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ i
     const int l = threadIdx.x;  // one wavefront
     const int r = l % 16, g = l / 16;
     auto bfw = [](float v) { return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v); };
+    // forward operands of the hidden layers 0..2 are built from c W and c b
+    const float c = kTanhScale;
     // layer 0: slots 0-5 W_hi, 6-11 W_hi, 12-17 W_lo, rest 0
     for (int mt = 0; mt < 4; ++mt) {
         const int m = 16 * mt + r;
@@ -97,7 +104,7 @@ __global__ void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ i
             float v = 0.0f;
             if (s < 18) {
                 const int f = s % 6;
-                const float wf = p[kOffW0 + m * kIn + f];
+                const float wf = c * p[kOffW0 + m * kIn + f];
                 const float hi = bf16_round(wf);
                 v = (s < 12) ? hi : bf16_round(wf - hi);
             }
@@ -110,28 +117,28 @@ __global__ void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ i
         const float* W = p + (layer == 1 ? kOffW1 : kOffW2);
         const int base = layer == 1 ? 16 : 48;
         for (int mt = 0; mt < 4; ++mt)
-            for (int c = 0; c < 2; ++c) {
+            for (int kc = 0; kc < 2; ++kc) {
                 const int m = 16 * mt + r;
                 uint32_t w[4] = {0, 0, 0, 0};
-                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(W[m * kW + perm_feature(c, g, j)]) << (16 * (j & 1));
-                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * c + q) * 64 + l] = w[q];
+                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(c * W[m * kW + perm_feature(kc, g, j)]) << (16 * (j & 1));
+                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * kc + q) * 64 + l] = w[q];
             }
     }
-    // layer 3: 6 output rows, rows 6..15 zero
-    for (int c = 0; c < 2; ++c) {
+    // layer 3 (output, unscaled): 6 output rows, rows 6..15 zero
+    for (int kc = 0; kc < 2; ++kc) {
         uint32_t w[4] = {0, 0, 0, 0};
         for (int j = 0; j < 8; ++j) {
-            const float v = r < kIn ? p[kOffW3 + r * kW + perm_feature(c, g, j)] : 0.0f;
+            const float v = r < kIn ? p[kOffW3 + r * kW + perm_feature(kc, g, j)] : 0.0f;
             w[j / 2] |= bfw(v) << (16 * (j & 1));
         }
-        for (int q = 0; q < 4; ++q) img[(80 + 4 * c + q) * 64 + l] = w[q];
+        for (int q = 0; q < 4; ++q) img[(80 + 4 * kc + q) * 64 + l] = w[q];
     }
     // biases (FP32 bit patterns)
     for (int layer = 0; layer < 3; ++layer) {
         const float* b = p + (layer == 0 ? kOffB0 : layer == 1 ? kOffB1 : kOffB2);
         for (int mt = 0; mt < 4; ++mt)
             for (int i = 0; i < 4; ++i)
-                img[(88 + 16 * layer + 4 * mt + i) * 64 + l] = __float_as_uint(b[16 * mt + 4 * g + i]);
+                img[(88 + 16 * layer + 4 * mt + i) * 64 + l] = __float_as_uint(c * b[16 * mt + 4 * g + i]);
     }
     for (int i = 0; i < 4; ++i) {
         const int row = 4 * g + i;
@@ -153,11 +160,11 @@ __global__ void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ i
         const float* W = p + (layer == 1 ? kOffW1 : kOffW2);
         const int base = layer == 2 ? 156 : 188;
         for (int mt = 0; mt < 4; ++mt)
-            for (int c = 0; c < 2; ++c) {
+            for (int kc = 0; kc < 2; ++kc) {
                 const int m = 16 * mt + r;
                 uint32_t w[4] = {0, 0, 0, 0};
-                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(W[perm_feature(c, g, j) * kW + m]) << (16 * (j & 1));
-                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * c + q) * 64 + l] = w[q];
+                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(W[perm_feature(kc, g, j) * kW + m]) << (16 * (j & 1));
+                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * kc + q) * 64 + l] = w[q];
             }
     }
 }
@@ -209,8 +216,8 @@ __device__ __forceinline__ void activate(const f32x4 (&d)[4], u32x4 (&h)[2]) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const f32x4 p = d[2 * c], q = d[2 * c + 1];
-        h[c] = u32x4{pack_bf16x2(tanh_f32(p[0]), tanh_f32(p[1])), pack_bf16x2(tanh_f32(p[2]), tanh_f32(p[3])),
-                     pack_bf16x2(tanh_f32(q[0]), tanh_f32(q[1])), pack_bf16x2(tanh_f32(q[2]), tanh_f32(q[3]))};
+        h[c] = u32x4{pack_bf16x2(tanh_scaled(p[0]), tanh_scaled(p[1])), pack_bf16x2(tanh_scaled(p[2]), tanh_scaled(p[3])),
+                     pack_bf16x2(tanh_scaled(q[0]), tanh_scaled(q[1])), pack_bf16x2(tanh_scaled(q[2]), tanh_scaled(q[3]))};
     }
 }
 
@@ -262,7 +269,9 @@ constexpr int kInferBlock = 256;
 // Persistent grid; each wavefront takes groups of 64 particles: lane column n
 // (= l % 16) of N-tile t holds particle base + 4n + t, so a lane's four
 // particles are contiguous in every bunch row.
-__global__ __launch_bounds__(kInferBlock) void k_mlp_infer(double* __restrict__ z, int64_t n, int64_t ld,
+// Two waves per SIMD: weights, biases and four tiles in flight fit in the
+// 256 architected VGPRs, with no accumulator-register round trips.
+__global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(double* __restrict__ z, int64_t n, int64_t ld,
                                                            const uint32_t* __restrict__ img, NormArgs na) {
     Net net;
     load_net(img, net);
@@ -591,7 +600,7 @@ __global__ __launch_bounds__(256) void k_grad_sum(const float* part, int nb, flo
 }
 
 // MSE over pairs [i0, i0 + n) (test split), FP64 block partials.
-__global__ __launch_bounds__(kInferBlock) void k_mlp_eval_loss(const double* __restrict__ zin,
+__global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_eval_loss(const double* __restrict__ zin,
                                                                const double* __restrict__ zout, int64_t ld,
                                                                int64_t i0, int64_t n,
                                                                const uint32_t* __restrict__ img, NormArgs na,

@@ -161,8 +161,9 @@ def test_training_curve_matches_oracle(hbl, orc, pairs):
     n, rec, out, xin, xout, _, _ = pairs
     s = hbl.Surrogate(12)
     p0 = s.get_params()
-    log = s.train(rec, out, n, batch=256, epochs=3, lr=3e-3, shuffle_seed=5)
-    _, _, olog = orc.mlp_train(orc.shape(), p0, xin, xout, batch=256, epochs=3, lr=3e-3, shuffle_seed=5, mode=1)
+    log = s.train(rec, out, n, batch=256, epochs=3, lr=3e-3, lr_final=3e-4, shuffle_seed=5)
+    _, _, olog = orc.mlp_train(orc.shape(), p0, xin, xout, batch=256, epochs=3, lr=3e-3, lr_final=3e-4,
+                               shuffle_seed=5, mode=1)
     assert np.all(np.isfinite(log))
     assert log[-1, 1] < 0.7 * log[0, 1]
     assert np.all(np.abs(log / olog - 1) < 0.1), (log, olog)
