@@ -29,6 +29,15 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 MLP_FLOP_PER_PARTICLE = 2 * (6 * 64 + 64 * 64 + 64 * 64 + 64 * 6)   # 17,920: dense layers, FMA = 2
+# VALU issue: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz full-rate FP32 lane-slots; a
+# transcendental (exp2, reciprocal) issues at quarter rate and costs 4 slots.
+VALU_PEAK_TSLOTS = 256 * 4 * 32 * 2.4e9 / 1e12                      # 78.6 T slots/s
+# tanh(a) = 1 - 2/(2^(c a) + 1): exp2 (4) + add (1) + reciprocal (4) + fma (1) = 10 slots,
+# 3 hidden layers x 64 activations per particle
+ALU_SLOTS_PER_PARTICLE = 3 * 64 * 10                                 # 1,920
+# HBM bytes per launch of the dominant kernel read from the FETCH_SIZE / WRITE_SIZE
+# counter runs (scaled by a plain copy); None until taken for the current kernel.
+TRAFFIC_BYTES_PER_LAUNCH = None
 
 
 def parse():
@@ -42,10 +51,11 @@ def parse():
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-single-stage", action="store_true", help="skip the single-stage (C4) study")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="short run for hardware-counter passes: one plain device copy of 2 x 1 GiB "
-                         "(calibration) and 3 launches of the surrogate inference kernel on the "
-                         "benchmark bunch (untrained weights), then exit")
+                    help="short run for hardware-counter passes: one plain device copy of 1 GiB "
+                         "(calibration), then the benchmark's four surrogate passes (inference "
+                         "with the gaps fused, untrained weights) on the benchmark bunch, twice")
     return ap.parse_args()
 
 
@@ -56,38 +66,50 @@ def pmc_probe(args):
     import workloads as W
     from paper_2402_17248_amd import hbl
 
+    from paper_2402_17248_amd.chain import Chain
+
     torch.cuda.set_device(0)
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")      # 1 GiB
     b = torch.empty_like(a)
     b.copy_(a)                                                           # reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
     wl = W.c5_chain(n=args.n)
-    sur = hbl.Surrogate(W.mlp_init_seed(1))
+    n = wl.bunch.n
+    chain = Chain(wl.beamline, wl.E_MeV)
     sig = wl.bunch.sigma
-    sur.set_norm([0.0] * 6 + list(sig) + [0.0] * 6 + list(sig))
-    z = hbl.new_bunch(wl.bunch.n)
-    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=wl.bunch.n)
-    for _ in range(3):
-        sur.apply(z, n=wl.bunch.n)
+    for k in range(chain.stage_count):
+        sur = hbl.Surrogate(W.mlp_init_seed(k + 1))
+        sur.set_norm([0.0] * 6 + list(sig) + [0.0] * 6 + list(sig))
+        sur.set_stage(chain.stage(k), chain.entry_ref(k))
+        chain.surrogates[k] = sur
+    z = hbl.new_bunch(n)
+    for _ in range(2):
+        hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
+        chain.run(z, n=n, use_surrogates=True)
     torch.cuda.synchronize()
-    log(f"pmc probe done: copy 1 GiB, 3 x k_mlp_infer on {wl.bunch.n} particles")
+    log(f"pmc probe done: copy 1 GiB, 2 x {chain.stage_count} surrogate passes on {n} particles")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_events(torch, fn, iters):
+def time_events(torch, fn, iters, setup=None):
     """Average duration of fn() by HIP events on torch's current stream, the
-    stream every library call below is enqueued on."""
-    s = torch.cuda.Event(enable_timing=True)
-    e = torch.cuda.Event(enable_timing=True)
-    s.record()
+    stream every library call below is enqueued on; setup() (untimed) runs
+    before each timed call."""
+    total = 0.0
     for _ in range(iters):
+        if setup is not None:
+            setup()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
         fn()
-    e.record()
-    torch.cuda.synchronize()
-    return s.elapsed_time(e) / iters * 1e-3
+        e.record()
+        torch.cuda.synchronize()
+        total += s.elapsed_time(e)
+    return total / iters * 1e-3
 
 
 def cpu_baseline(wl, chain, budget_s):
@@ -123,6 +145,94 @@ def cpu_baseline(wl, chain, budget_s):
     return {"value": m / t, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} particles of the {wl.bunch.n}-particle bunch through the full staged "
                       f"beamline (lattice gaps + 4 surrogate stages), serial FP64 oracle, {t:.1f} s"}
+
+
+def single_stage_study(args, log):
+    """C4: the 1 -> 10 GeV stage behind its entrance triplet.  A surrogate is
+    trained on 2^20 pairs of the fine-step stage (seed 3) and applied to a
+    fresh 1e7-particle bunch (seed 4); accuracy and speed against the
+    2000-substep stage, and against the fine-step stage at the substep count
+    whose emittance error (vs a 32,000-substep reference) equals the
+    surrogate's."""
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+
+    wl = W.c3_stage()
+    sig = wl.bunch.sigma
+    stage = wl.beamline[1]
+
+    def through_triplet(n, seed):
+        z = hbl.new_bunch(n)
+        hbl.fill_gaussian(z, seed, (0.0,) * 6, sig, n=n)
+        ref = hbl.Ref.from_energy(wl.E_MeV)
+        hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
+        return z, ref
+
+    npairs = W.C3_PAIR_N
+    zout, ref = through_triplet(npairs, W.C3_PAIR_SEED)
+    zin = hbl.new_bunch(npairs)
+    entry = ref.copy()
+    hbl.apply_stage(zout, stage, ref, record=zin, n=npairs)
+    sur = hbl.Surrogate(W.mlp_init_seed(0))
+    t0 = time.perf_counter()
+    curve = sur.train(zin, zout, npairs, batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR,
+                      lr_final=1e-5, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sur.set_stage(stage, entry)
+    del zin, zout
+
+    N = W.C4_INFER_N
+    x, r0 = through_triplet(N, W.C4_INFER_SEED)
+    f = x.clone()
+    hbl.apply_stage(f, stage, r0.copy(), n=N)
+    s = x.clone()
+    sur.apply(s, r0.copy(), n=N)
+    rms, cen, eps = hbl.compare(s, f, n=N)
+    t_inf = time_events(torch, lambda: sur.apply(s, r0.copy(), n=N), 10)
+    t_fine = time_events(torch, lambda: hbl.apply_stage(f, stage, r0.copy(), n=N), 3)
+    del s, f
+
+    # equal-error comparator on the first 1e6 particles
+    m = 1_000_000
+    xm = x[:, :m].contiguous()
+    conv = xm.clone()
+    hbl.apply_stage(conv, hbl.Element(5, 32000, stage.L, 0, 0, 0, stage.n0_m3, stage.dE_MeV), r0.copy(), n=m)
+    sm = xm.clone()
+    sur.apply(sm, r0.copy(), n=m)
+    err_s = max(abs(e) for e in hbl.compare(sm, conv, n=m)[2][:2])
+
+    def err_fine(nsub):
+        fm = xm.clone()
+        hbl.apply_stage(fm, hbl.Element(5, nsub, stage.L, 0, 0, 0, stage.n0_m3, stage.dE_MeV), r0.copy(), n=m)
+        return max(abs(e) for e in hbl.compare(fm, conv, n=m)[2][:2])
+
+    lo, hi = 50, 32000
+    if err_fine(lo) <= err_s:
+        hi = lo
+    while hi - lo > max(1, lo // 50):
+        mid = (lo + hi) // 2
+        if err_fine(mid) <= err_s:
+            hi = mid
+        else:
+            lo = mid
+    n_eq = hi
+    el_eq = hbl.Element(5, n_eq, stage.L, 0, 0, 0, stage.n0_m3, stage.dE_MeV)
+    f2 = x.clone()
+    t_fine_eq = time_events(torch, lambda: hbl.apply_stage(f2, el_eq, r0.copy(), n=N), 3)
+    out = {"workload": "stage_1to10GeV_1e7", "particles": N, "epochs": args.epochs,
+           "train_seconds": t_train, "final_loss_train_test": [float(v) for v in curve[-1]],
+           "eps_rel_xyt_vs_2000_substeps": eps, "rms_over_sigma": rms, "centroid_over_sigma": cen,
+           "inference_ms": t_inf * 1e3, "fine_step_2000_ms": t_fine * 1e3, "speedup_vs_2000": t_fine / t_inf,
+           "eps_err_vs_converged_32000": {"surrogate": err_s, "fine_step_at_equal_error_nsub": n_eq},
+           "fine_step_equal_error_ms": t_fine_eq * 1e3, "speedup_at_equal_error": t_fine_eq / t_inf,
+           "inference_particles_per_s": N / t_inf}
+    log(f"C4 single stage: eps_rel {eps}, rms {rms}; inference {t_inf*1e3:.3f} ms vs fine-step "
+        f"{t_fine*1e3:.3f} ms ({t_fine/t_inf:.1f}x); equal-error fine-step nsub {n_eq} "
+        f"({t_fine_eq*1e3:.3f} ms, {t_fine_eq/t_inf:.1f}x)")
+    return out, t_inf
 
 
 def main():
@@ -164,24 +274,37 @@ def main():
     z = hbl.new_bunch(n)
     out27 = torch.empty(27, dtype=torch.float64, device="cuda")
 
-    def step(use_sur):
+    n_pass = len(chain.passes())        # stage passes per step, one kernel launch each
+
+    def step(use_sur, ev=None):
         hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
+        if ev is not None:
+            ev[0].record()
         chain.run(z, n=n, use_surrogates=use_sur)
+        if ev is not None:
+            ev[1].record()
         hbl.moments_async(z, out27, n=n)
 
     def timed(use_sur, steps, warmup):
+        """Wall time per step over exactly `steps` steps, and the average
+        duration of one stage-pass launch from HIP events recorded on the
+        library's stream around the passes inside those same steps."""
         for _ in range(warmup):
             step(use_sur)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
-            step(use_sur)
+        for k in range(steps):
+            step(use_sur, evs[k])
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / steps
+        dt = (time.perf_counter() - t) / steps
+        per_launch = sum(a.elapsed_time(b) for a, b in evs) * 1e-3 / steps / n_pass
+        return dt, per_launch
 
-    dt_sur = timed(True, args.steps, args.warmup)
+    dt_sur, t_inf = timed(True, args.steps, args.warmup)
     log(f"surrogate chain: {dt_sur * 1e3:.3f} ms/step, {n / dt_sur:.4g} particles/s")
-    dt_fine = timed(False, args.fine_steps, 1)
+    dt_fine, t_fs = timed(False, args.fine_steps, 1)
     log(f"fine-step chain: {dt_fine * 1e3:.3f} ms/step, {n / dt_fine:.4g} particles/s")
 
     # ---- accuracy of the surrogate chain against the fine-step chain, same input
@@ -194,15 +317,17 @@ def main():
     log(f"surrogate vs fine-step chain: eps_rel x,y,t = {eps_rel}, rms/sigma = {rms}")
     del zs
 
-    # ---- dominant kernel: surrogate inference, timed alone on the stream
-    sur0 = chain.surrogates[0]
-    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
-    t_inf = time_events(torch, lambda: sur0.apply(z, n=n), max(3, args.steps))
-    fine_stage = chain.stage(0)
-    t_fs = time_events(torch, lambda: hbl.apply_stage(z, fine_stage, chain.entry_ref(0), n=n), 2)
+    single = None
+    if not args.no_single_stage:
+        single, _ = single_stage_study(args, log)
+
+    # ---- dominant kernel: surrogate inference with the gaps fused (k_mlp_infer,
+    # one launch per stage pass), timed inside the timed steps above
+    alu_achieved = ALU_SLOTS_PER_PARTICLE * n / t_inf / 1e12
     mfma_achieved = MLP_FLOP_PER_PARTICLE * n / t_inf / 1e12
-    log(f"inference kernel: {t_inf * 1e3:.3f} ms per stage ({n / t_inf:.4g} particles/s); "
-        f"fine-step stage kernel: {t_fs * 1e3:.3f} ms; single-stage speed-up {t_fs / t_inf:.1f}x")
+    log(f"inference kernel (gaps fused): {t_inf * 1e3:.3f} ms per launch ({n / t_inf:.4g} particles/s, "
+        f"{alu_achieved:.1f} T VALU slots/s, {mfma_achieved:.0f} TFLOP/s dense); fine-step stage "
+        f"kernel: {t_fs * 1e3:.3f} ms per launch; per-stage speed-up {t_fs / t_inf:.1f}x")
 
     cpu = None
     if not args.no_cpu:
@@ -221,16 +346,20 @@ def main():
                                 "batch": W.TRAIN_BATCH, "lr": W.TRAIN_LR, "lr_final": 1e-5,
                                 "seconds_total": t_train,
                                 "final_test_loss": [float(c[-1, 1]) for c in curves]}},
-        "fine_step_path": {"value": n / dt_fine, "ms_per_step": dt_fine * 1e3, "nsub": fine_stage.nsub,
+        "fine_step_path": {"value": n / dt_fine, "ms_per_step": dt_fine * 1e3, "nsub": chain.stage(0).nsub,
                            "speedup_surrogate": dt_fine / dt_sur},
         "accuracy_vs_fine_step": {"eps_rel_xyt": eps_rel, "rms_over_sigma": rms,
                                   "centroid_over_sigma": cen},
-        "single_stage": {"inference_ms": t_inf * 1e3, "fine_step_ms": t_fs * 1e3,
-                         "speedup": t_fs / t_inf},
+        "stage_pass_kernels": {"inference_ms": t_inf * 1e3, "fine_step_ms": t_fs * 1e3,
+                               "speedup": t_fs / t_inf, "launches_per_step": n_pass,
+                               "dense_mfma_tflops": mfma_achieved,
+                               "dense_mfma_frac": mfma_achieved / BF16_PEAK_TFLOPS},
+        "single_stage_c4": single,
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
-        "roofline": {"bound": "mfma", "achieved": mfma_achieved, "peak": BF16_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": mfma_achieved / BF16_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_mlp_infer (surrogate inference)"},
+        "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,
+                     "unit": "T VALU slots/s", "frac": alu_achieved / VALU_PEAK_TSLOTS,
+                     "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                     "kernel": "k_mlp_infer<gaps> (surrogate inference, transport gaps fused)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

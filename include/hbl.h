@@ -137,6 +137,17 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
 hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* stage,
                            hbl_ref* ref, double* record, int64_t record_ld, hbl_stream stream);
 
+/* ASYNC.  One pass over the bunch equivalent to hbl_push_lattice(pre),
+ * hbl_apply_stage(stage), hbl_push_lattice(post): the transport gaps before
+ * and after the stage (§4, Fig. 1: stages joined by transport sections) are
+ * applied in registers by the stage kernel.  pre and post are nullable; pre
+ * must be compiled for ref->gamma, post for the stage's exit gamma.  record
+ * (nullable) receives the stage input, i.e. the bunch after pre.  Results
+ * are bitwise those of the three separate calls. */
+hbl_status hbl_apply_stage_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
+                                const hbl_element* stage, const hbl_lattice* post, hbl_ref* ref,
+                                double* record, int64_t record_ld, hbl_stream stream);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 /* SYNC.  Beam moments (§4): mean6[j] = <z_j>; cov21 = centred population
@@ -237,6 +248,14 @@ hbl_status hbl_surrogate_loss_grad(hbl_surrogate* m, const double* zin, const do
  * Needs a normalisation (set or trained). */
 hbl_status hbl_surrogate_apply(double* z, int64_t n, int64_t ld, const hbl_surrogate* m, hbl_ref* ref,
                                hbl_stream stream);
+
+/* ASYNC.  hbl_push_lattice(pre), hbl_surrogate_apply, hbl_push_lattice(post)
+ * in one pass over the bunch (the gaps applied in registers by the inference
+ * kernel).  Needs a declared stage; pre compiled for ref->gamma, post for
+ * the exit gamma; both nullable.  Bitwise equal to the separate calls. */
+hbl_status hbl_surrogate_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
+                                    const hbl_surrogate* m, const hbl_lattice* post, hbl_ref* ref,
+                                    hbl_stream stream);
 
 /* Save / load the model (shape, normalisation, stage, FP32 parameters, Adam
  * moments and step) to a binary file with a checksum.  HBL_EIO on I/O or

@@ -78,27 +78,62 @@ class Chain:
             del zin, zout
         return logs
 
+    def passes(self):
+        """Group the segments into bunch passes: each stage absorbs the lattice
+        segment right before it (its entrance gap) and, for the last segment,
+        the one right after it (the exit gap).  Items: ("lattice", L) or
+        ("stage", (pre, k, stage, post))."""
+        out, segs, i, k = [], self.segments, 0, 0
+        while i < len(segs):
+            kind, v = segs[i]
+            if kind == "lattice" and not (i + 1 < len(segs) and segs[i + 1][0] == "stage"):
+                out.append(("lattice", v))
+                i += 1
+                continue
+            pre = None
+            if kind == "lattice":
+                pre, i = v, i + 1
+            st = segs[i][1]
+            i += 1
+            post = None
+            if i == len(segs) - 1 and segs[i][0] == "lattice":
+                post, i = segs[i][1], i + 1
+            out.append(("stage", (pre, k, st, post)))
+            k += 1
+        return out
+
     def run(self, z, n=None, use_surrogates=False, stop_before_stage: Optional[int] = None,
-            record=None, fused=True, stream=None) -> hbl.Ref:
+            record=None, fused=True, gaps_fused=True, stream=None) -> hbl.Ref:
         """Push z in place.  stop_before_stage=k stops at the entrance of stage k
         (0-based); with record given, stage k is then applied with the input
-        recorded (training pairs)."""
+        recorded (training pairs).  gaps_fused runs each gap in its stage's
+        kernel (one bunch pass per stage); fused=False pushes lattices element
+        by element (comparator).  All variants give bitwise equal results."""
         ref = hbl.Ref.from_energy(self.E_MeV)
-        k = 0
-        for kind, v in self.segments:
+        for kind, v in self.passes():
             if kind == "lattice":
                 v.push(z, ref, fused=fused, n=n, stream=stream)
                 continue
-            if stop_before_stage is not None and k == stop_before_stage:
+            pre, k, st, post = v
+            if not (gaps_fused and fused):
+                if pre is not None:
+                    pre.push(z, ref, fused=fused, n=n, stream=stream)
+                pre = None
+            stopping = stop_before_stage is not None and k == stop_before_stage
+            if stopping:
                 if record is not None:
-                    hbl.apply_stage(z, v, ref, record=record, n=n, stream=stream)
+                    hbl.apply_stage(z, st, ref, record=record, n=n, stream=stream, pre=pre)
+                elif pre is not None:
+                    pre.push(z, ref, n=n, stream=stream)
                 return ref
+            post_now = post if (gaps_fused and fused) else None
             if use_surrogates:
                 sur = self.surrogates[k]
                 if sur is None:
                     raise RuntimeError(f"stage {k} has no surrogate attached")
-                sur.apply(z, ref, n=n, stream=stream)
+                sur.apply(z, ref, n=n, stream=stream, pre=pre, post=post_now)
             else:
-                hbl.apply_stage(z, v, ref, n=n, stream=stream)
-            k += 1
+                hbl.apply_stage(z, st, ref, n=n, stream=stream, pre=pre, post=post_now)
+            if post is not None and post_now is None:
+                post.push(z, ref, fused=fused, n=n, stream=stream)
         return ref

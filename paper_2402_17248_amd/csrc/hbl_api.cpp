@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/hbl.h"
-#include "hbl_internal.hpp"
+#include "hbl_elements.hpp"
 
 namespace hbl {
 
@@ -373,8 +373,31 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
     return HBL_OK;
 }
 
-hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* stage, hbl_ref* ref,
-                           double* record, int64_t record_ld, hbl_stream stream) {
+}  // extern "C"
+
+namespace {
+
+LatticeView view_of(const hbl_lattice* lat) {
+    LatticeView v{nullptr, nullptr, 0};
+    if (lat) {
+        v.kinds = lat->d_kinds;
+        v.coef = lat->d_coef;
+        v.n = lat->n_elem;
+    }
+    return v;
+}
+
+// A gap lattice must be compiled for the reference energy it is applied at.
+hbl_status check_gap(const hbl_lattice* lat, double gamma, const char* what) {
+    if (!lat) return HBL_OK;
+    HBL_REQUIRE(lat->gamma == gamma, "%s lattice compiled for gamma %.17g, applied at gamma %.17g", what,
+                lat->gamma, gamma);
+    return HBL_OK;
+}
+
+hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice* pre, const hbl_element* stage,
+                            const hbl_lattice* post, hbl_ref* ref, double* record, int64_t record_ld,
+                            hbl_stream stream) {
     clear_error();
     if (hbl_status st = check_bunch(z, n, ld, "apply_stage")) return st;
     HBL_REQUIRE(stage, "apply_stage: NULL stage");
@@ -387,6 +410,8 @@ hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* 
     const double g_in = ref->gamma;
     const double g_out = g_in + stage->dE_MeV / ref->mass_MeV;
     HBL_REQUIRE(g_out > 1.0 + 1e-6, "apply_stage: exit gamma %g must exceed 1", g_out);
+    if (hbl_status st = check_gap(pre, g_in, "apply_stage: entrance")) return st;
+    if (hbl_status st = check_gap(post, g_out, "apply_stage: exit")) return st;
     if (record) {
         if (hbl_status st = check_bunch(record, n, record_ld, "apply_stage record")) return st;
         const uintptr_t a0 = (uintptr_t)z, a1 = a0 + (uintptr_t)(5 * ld + n) * 8;
@@ -432,11 +457,27 @@ hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* 
     if (n > 0) {
         const double* tab = stage_table(g_in, gp, h, N, &st);
         if (!tab) return st;
-        HBL_HIP(launch_stage(z, n, ld, record, record_ld, p, tab, (hipStream_t)stream));
+        HBL_HIP(launch_stage(z, n, ld, record, record_ld, p, tab, view_of(pre), view_of(post),
+                             (hipStream_t)stream));
     }
     ref->gamma = g_out;
-    ref->s += L;
+    ref->s += (pre ? pre->length : 0.0) + L + (post ? post->length : 0.0);
     return HBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* stage, hbl_ref* ref,
+                           double* record, int64_t record_ld, hbl_stream stream) {
+    return apply_stage_impl(z, n, ld, nullptr, stage, nullptr, ref, record, record_ld, stream);
+}
+
+hbl_status hbl_apply_stage_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
+                                const hbl_element* stage, const hbl_lattice* post, hbl_ref* ref,
+                                double* record, int64_t record_ld, hbl_stream stream) {
+    return apply_stage_impl(z, n, ld, pre, stage, post, ref, record, record_ld, stream);
 }
 
 hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out27, hbl_stream stream) {
@@ -790,24 +831,48 @@ hbl_status hbl_surrogate_set_stage(hbl_surrogate* m, const hbl_element* stage, c
     return HBL_OK;
 }
 
-hbl_status hbl_surrogate_apply(double* z, int64_t n, int64_t ld, const hbl_surrogate* m, hbl_ref* ref,
-                               hbl_stream stream) {
+}  // extern "C"
+
+namespace {
+
+hbl_status surrogate_apply_impl(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
+                                const hbl_surrogate* m, const hbl_lattice* post, hbl_ref* ref,
+                                hbl_stream stream) {
     clear_error();
     if (hbl_status st = check_bunch(z, n, ld, "surrogate_apply")) return st;
     HBL_REQUIRE(m, "surrogate_apply: NULL surrogate");
     if (!m->has_norm) { set_error(HBL_ESTATE, "surrogate_apply: no normalisation set or trained"); return HBL_ESTATE; }
+    HBL_REQUIRE(!(pre || post) || m->has_stage, "surrogate_apply: gap lattices need a declared stage");
     if (m->has_stage) {
         if (hbl_status st = check_ref(ref)) return st;
         HBL_REQUIRE(fabs(ref->gamma / m->gamma_in - 1.0) < 1e-12,
                     "surrogate_apply: reference gamma %.17g differs from the trained entry gamma %.17g",
                     ref->gamma, m->gamma_in);
+        if (hbl_status st = check_gap(pre, ref->gamma, "surrogate_apply: entrance")) return st;
+        if (hbl_status st = check_gap(post, ref->gamma + m->dE_MeV / ref->mass_MeV, "surrogate_apply: exit"))
+            return st;
     }
-    if (n > 0) HBL_HIP(launch_mlp_infer(z, n, ld, m->d_img, m->norm, (hipStream_t)stream));
+    if (n > 0) HBL_HIP(launch_mlp_infer(z, n, ld, m->d_img, m->norm, view_of(pre), view_of(post), (hipStream_t)stream));
     if (m->has_stage) {
         ref->gamma += m->dE_MeV / ref->mass_MeV;
-        ref->s += m->L;
+        ref->s += (pre ? pre->length : 0.0) + m->L + (post ? post->length : 0.0);
     }
     return HBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_surrogate_apply(double* z, int64_t n, int64_t ld, const hbl_surrogate* m, hbl_ref* ref,
+                               hbl_stream stream) {
+    return surrogate_apply_impl(z, n, ld, nullptr, m, nullptr, ref, stream);
+}
+
+hbl_status hbl_surrogate_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
+                                    const hbl_surrogate* m, const hbl_lattice* post, hbl_ref* ref,
+                                    hbl_stream stream) {
+    return surrogate_apply_impl(z, n, ld, pre, m, post, ref, stream);
 }
 
 hbl_status hbl_surrogate_loss_grad(hbl_surrogate* m, const double* zin, const double* zout, int64_t ld,

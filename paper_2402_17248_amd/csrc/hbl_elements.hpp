@@ -1,0 +1,83 @@
+// Device-side first-order element maps shared by the tracking, stage and
+// surrogate kernels (the coefficient records are built on the host, see
+// ElemCoef in hbl_internal.hpp).  Every multiply-add is an explicit fma():
+// the kernels are compiled with -ffp-contract=off, so every kernel that
+// applies an element executes the same operations in the same order.
+#pragma once
+
+#include "hbl_internal.hpp"
+
+namespace hbl {
+
+struct P6 {
+    double x, y, t, px, py, pt;
+};
+
+__device__ __forceinline__ void el_drift(P6& p, const double* c) {
+    p.x = fma(c[0], p.px, p.x);
+    p.y = fma(c[0], p.py, p.y);
+    p.t = fma(c[1], p.pt, p.t);
+}
+
+__device__ __forceinline__ void el_quad(P6& p, const double* c) {
+    const double x = p.x, px = p.px, y = p.y, py = p.py;
+    p.x = fma(c[1], px, c[0] * x);
+    p.px = fma(c[3], px, c[2] * x);
+    p.y = fma(c[5], py, c[4] * y);
+    p.py = fma(c[7], py, c[6] * y);
+    p.t = fma(c[8], p.pt, p.t);
+}
+
+__device__ __forceinline__ void el_sbend(P6& p, const double* c) {
+    const double x = p.x, px = p.px, pt = p.pt;
+    p.x = fma(c[2], pt, fma(c[1], px, c[0] * x));
+    p.px = fma(c[5], pt, fma(c[4], px, c[3] * x));
+    p.y = fma(c[9], p.py, p.y);
+    p.t = fma(c[8], pt, fma(c[7], px, fma(c[6], x, p.t)));
+}
+
+__device__ __forceinline__ void el_lens(P6& p, const double* c) {
+    p.px = fma(c[0], p.x, p.px);
+    p.py = fma(c[0], p.y, p.py);
+}
+
+// A compiled element sequence (device coefficient table), passed by value.
+struct LatticeView {
+    const int32_t* kinds;
+    const double* coef;
+    int32_t n;
+};
+
+// Apply the sequence to one particle; the kind and coefficients are uniform
+// across the wavefront (scalar loads, scalar branch).
+__device__ __forceinline__ void apply_elements(P6& p, const LatticeView& lv) {
+    for (int32_t e = 0; e < lv.n; ++e) {
+        const double* c = lv.coef + (int64_t)e * kCoef;
+        switch (lv.kinds[e]) {
+            case kDrift: el_drift(p, c); break;
+            case kQuad: el_quad(p, c); break;
+            case kSbend: el_sbend(p, c); break;
+            default: el_lens(p, c); break;
+        }
+    }
+}
+
+__device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {
+    p.x = z[i];
+    p.y = z[ld + i];
+    p.t = z[2 * ld + i];
+    p.px = z[3 * ld + i];
+    p.py = z[4 * ld + i];
+    p.pt = z[5 * ld + i];
+}
+
+__device__ __forceinline__ void store6(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
+    z[i] = p.x;
+    z[ld + i] = p.y;
+    z[2 * ld + i] = p.t;
+    z[3 * ld + i] = p.px;
+    z[4 * ld + i] = p.py;
+    z[5 * ld + i] = p.pt;
+}
+
+}  // namespace hbl

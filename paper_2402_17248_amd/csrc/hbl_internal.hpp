@@ -51,8 +51,10 @@ hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const int32_t*
                                 const double* coef, int32_t n_elem, hipStream_t s);
 hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind,
                                   const ElemCoef& c, hipStream_t s);
+struct LatticeView;
 hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
-                        const StageParams& p, const double* gmid, hipStream_t s);
+                        const StageParams& p, const double* gmid, const LatticeView& pre,
+                        const LatticeView& post, hipStream_t s);
 
 // Reductions.  `ws` is device scratch of at least reduce_ws_bytes(n) bytes.
 size_t reduce_ws_bytes(int64_t n);
@@ -66,7 +68,7 @@ int mlp_nparams();
 int mlp_image_words();
 hipError_t launch_mlp_pack(const float* params, uint32_t* img, hipStream_t s);
 hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* img, const double* norm24,
-                            hipStream_t s);
+                            const LatticeView& pre, const LatticeView& post, hipStream_t s);
 hipError_t launch_train_step(const double* zin, const double* zout, int64_t ld, const int32_t* idx,
                              int32_t batch, const uint32_t* img, float* part, float* loss_part,
                              const double* norm24, hipStream_t s);

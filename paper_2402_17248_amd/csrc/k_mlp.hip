@@ -20,7 +20,7 @@
 // W x ~ W_hi x_hi + W_hi x_lo + W_lo x_hi (slots 0-5, 6-11, 12-17), so the
 // input keeps ~16 significant bits.  Hidden activations are bf16; the output
 // layer result stays FP32 and is de-normalised in FP64.
-#include "hbl_internal.hpp"
+#include "hbl_elements.hpp"
 
 namespace hbl {
 namespace {
@@ -266,66 +266,76 @@ __device__ __forceinline__ u32x4 input_operand(const float (&xn)[6], int g) {
 
 constexpr int kInferBlock = 256;
 
-// Persistent grid; each wavefront takes groups of 64 particles: lane column n
-// (= l % 16) of N-tile t holds particle base + 4n + t, so a lane's four
-// particles are contiguous in every bunch row.
-// Two waves per SIMD: weights, biases and four tiles in flight fit in the
-// 256 architected VGPRs, with no accumulator-register round trips.
-__global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(double* __restrict__ z, int64_t n, int64_t ld,
-                                                           const uint32_t* __restrict__ img, NormArgs na) {
+// Persistent grid; each wavefront takes groups of 64 particles, lane l owning
+// particle base + l (tile l / 16, column l % 16): one coalesced load and store
+// per bunch row, the transport gap before the stage (pre) and after it (post)
+// applied to the owned particle in registers.  The owner forms the bf16
+// hi/lo words of its normalised coordinates; every lane then gathers the
+// layer-0 operand of each tile from that tile's owner lanes, and after the
+// network each owner gathers its six outputs (rows 0-3 live in lane group 0,
+// rows 4-5 in lane group 1) -- cross-lane moves only, no redundant loads.
+template <bool GAPS>
+__global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(
+    double* __restrict__ z, int64_t n, int64_t ld, const uint32_t* __restrict__ img, NormArgs na,
+    LatticeView pre, LatticeView post) {
     Net net;
     load_net(img, net);
     const int l = threadIdx.x & 63, col = l % 16, g = l / 16;
     const int64_t waves = (int64_t)gridDim.x * (kInferBlock / 64);
     const int64_t wave = (int64_t)blockIdx.x * (kInferBlock / 64) + (threadIdx.x >> 6);
     for (int64_t base = wave * 64; base < n; base += waves * 64) {
-        const int64_t p0 = base + 4 * col;
-        const bool full = base + 64 <= n;
-        double x[4][6];
+        const int64_t i = base + l;
+        const bool live = i < n;
+        P6 p;
+        if (live) load6(z, ld, i, p);
+        else p = P6{na.mu_in[0], na.mu_in[1], na.mu_in[2], na.mu_in[3], na.mu_in[4], na.mu_in[5]};
+        if (GAPS) apply_elements(p, pre);
+        const double pv[6] = {p.x, p.y, p.t, p.px, p.py, p.pt};
+        uint32_t hw[3], lw[3];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const double* row = z + j * ld;
-            if (full) {
-                const double2 a = *reinterpret_cast<const double2*>(row + p0);
-                const double2 b = *reinterpret_cast<const double2*>(row + p0 + 2);
-                x[0][j] = a.x; x[1][j] = a.y; x[2][j] = b.x; x[3][j] = b.y;
-            } else {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) x[t][j] = (p0 + t < n) ? row[p0 + t] : na.mu_in[j];
-            }
+        for (int q = 0; q < 3; ++q) {
+            const float a = (float)((pv[2 * q] - na.mu_in[2 * q]) * na.inv_sd_in[2 * q]);
+            const float b = (float)((pv[2 * q + 1] - na.mu_in[2 * q + 1]) * na.inv_sd_in[2 * q + 1]);
+            const float ah = bf16_round(a), bh = bf16_round(b);
+            hw[q] = pack_bf16x2(ah, bh);
+            lw[q] = pack_bf16x2(a - ah, b - bh);
         }
         f32x4 y[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            float xn[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) xn[j] = (float)((x[t][j] - na.mu_in[j]) * na.inv_sd_in[j]);
-            y[t] = forward_tile(net, input_operand(xn, g));
+            const int src = 16 * t + col;
+            const uint32_t h0 = __shfl(hw[0], src, 64), h1 = __shfl(hw[1], src, 64), h2 = __shfl(hw[2], src, 64);
+            const uint32_t l0 = __shfl(lw[0], src, 64), l1 = __shfl(lw[1], src, 64), l2 = __shfl(lw[2], src, 64);
+            // K slots: 0-5 hi, 6-11 lo, 12-17 hi (see the file comment)
+            const u32x4 v0 = {h0, h1, h2, l0}, v1 = {l1, l2, h0, h1}, v2 = {h2, 0u, 0u, 0u};
+            const u32x4 zero = {0u, 0u, 0u, 0u};
+            y[t] = forward_tile(net, g == 0 ? v0 : g == 1 ? v1 : g == 2 ? v2 : zero);
         }
-        // lane group 0 holds output rows 0..3, group 1 rows 4..5
-        if (g < 2) {
+        float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int j = 4 * g + i;
-                if (j < kIn) {
-                    double* row = z + j * ld;
-                    double o[4];
+        for (int t = 0; t < 4; ++t) {
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) o[t] = fma(na.sd_out[j], (double)y[t][i], na.mu_out[j]);
-                    if (full) {
-                        *reinterpret_cast<double2*>(row + p0) = double2{o[0], o[1]};
-                        *reinterpret_cast<double2*>(row + p0 + 2) = double2{o[2], o[3]};
-                    } else {
+            for (int r = 0; r < 4; ++r) {
+                const float v = __shfl(y[t][r], col, 64);
+                if (g == t) o[r] = v;
+            }
 #pragma unroll
-                        for (int t = 0; t < 4; ++t)
-                            if (p0 + t < n) row[p0 + t] = o[t];
-                    }
-                }
+            for (int r = 0; r < 2; ++r) {
+                const float v = __shfl(y[t][r], 16 + col, 64);
+                if (g == t) o[4 + r] = v;
             }
         }
+        P6 q;
+        q.x = fma(na.sd_out[0], (double)o[0], na.mu_out[0]);
+        q.y = fma(na.sd_out[1], (double)o[1], na.mu_out[1]);
+        q.t = fma(na.sd_out[2], (double)o[2], na.mu_out[2]);
+        q.px = fma(na.sd_out[3], (double)o[3], na.mu_out[3]);
+        q.py = fma(na.sd_out[4], (double)o[4], na.mu_out[4]);
+        q.pt = fma(na.sd_out[5], (double)o[5], na.mu_out[5]);
+        if (GAPS) apply_elements(q, post);
+        if (live) store6(z, ld, i, q);
     }
 }
-
 
 // ================================================================ training
 // One training step over a batch (§3: MSE of Eq. (4), Adam): k_train_step
@@ -748,14 +758,19 @@ hipError_t launch_eval_loss(const double* zin, const double* zout, int64_t ld, i
 }
 
 hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* img, const double* norm24,
-                            hipStream_t s) {
+                            const LatticeView& pre, const LatticeView& post, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const NormArgs na = make_norm(norm24);
     int64_t groups = (n + 63) / 64;
     int64_t blocks = (groups + 3) / 4;
     const int64_t cap = 256 * 2;  // persistent: two 4-wave blocks per CU
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na);
+    if (pre.n > 0 || post.n > 0)
+        hipLaunchKernelGGL(k_mlp_infer<true>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na,
+                           pre, post);
+    else
+        hipLaunchKernelGGL(k_mlp_infer<false>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na,
+                           pre, post);
     return hipGetLastError();
 }
 

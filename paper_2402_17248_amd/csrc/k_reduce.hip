@@ -9,8 +9,8 @@
 //  2. the 64 lanes of a wavefront merge their sums as double-double pairs
 //     (error-free TwoSum) through cross-lane shuffles, the waves of a block
 //     through LDS, and each block writes NV double-double partials;
-//  3. one block merges the partials in double-double and forms
-//     mean = shift + S/n and cov = (P - S_j S_k / n) / n.
+//  3. one block per value merges the block partials in double-double; a
+//     final thread forms mean = shift + S/n and cov = (P - S_j S_k / n) / n.
 // Compiled with -ffp-contract=off: the TwoSum sequences must not be fused.
 #include "hbl_internal.hpp"
 
@@ -100,6 +100,30 @@ struct MomentsOp {
 #pragma unroll
         for (int j = 0; j < 6; ++j) sh[j] = z[j * ld];
     }
+    __device__ __forceinline__ void add2(int64_t i, int64_t k, double (&acc)[NV]) const {
+        double a[6], b[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            a[j] = z[j * ld + i];
+            b[j] = z[j * ld + k];
+        }
+        accumulate(a, acc);
+        accumulate(b, acc);
+    }
+    __device__ __forceinline__ void accumulate(const double (&v)[6], double (&acc)[NV]) const {
+        double d[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) d[j] = v[j] - sh[j];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[j] += d[j];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+#pragma unroll
+            for (int k = j; k < 6; ++k) {
+                const int q = 6 + j * 6 - j * (j - 1) / 2 + (k - j);
+                acc[q] = fma(d[j], d[k], acc[q]);
+            }
+    }
     __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
         double d[6];
 #pragma unroll
@@ -122,6 +146,18 @@ struct Diff2Op {
     const double* zf;
     int64_t ld;
     __device__ __forceinline__ void init() {}
+    __device__ __forceinline__ void add2(int64_t i, int64_t k, double (&acc)[NV]) const {
+        double a[6], b[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            a[j] = zs[j * ld + i] - zf[j * ld + i];
+            b[j] = zs[j * ld + k] - zf[j * ld + k];
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[j] = fma(a[j], a[j], acc[j]);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[j] = fma(b[j], b[j], acc[j]);
+    }
     __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
@@ -140,7 +176,13 @@ __global__ __launch_bounds__(kBlock) void k_partials(Op op, int64_t n, DD* __res
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) op.add(i, acc);
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // two particles per iteration: both loads are in flight before either
+    // feeds the (fixed-order) accumulation
+    for (; i + stride < n; i += 2 * stride) {
+        op.add2(i, i + stride, acc);
+    }
+    for (; i < n; i += stride) op.add(i, acc);
     DD v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = DD{acc[q], 0.0};
@@ -153,30 +195,25 @@ __global__ __launch_bounds__(kBlock) void k_partials(Op op, int64_t n, DD* __res
     }
 }
 
-// One block: total of nb partials per value, fixed order.
-template <int NV>
-__device__ void merge_partials(const DD* __restrict__ part, int nb, DD* tot) {
+// Block q merges the nb partials of value q (fixed order: strided per-thread
+// sums, then a tree), writing one double-double total.
+__global__ __launch_bounds__(kBlock) void k_merge(const DD* __restrict__ part, int nb, int nv,
+                                                  DD* __restrict__ tot) {
     __shared__ DD red[kBlock];
-    for (int q = 0; q < NV; ++q) {
-        DD s{0.0, 0.0};
-        for (int b = threadIdx.x; b < nb; b += kBlock) s = dd_add(s, part[(int64_t)b * NV + q]);
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = kBlock / 2; w >= 1; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] = dd_add(red[threadIdx.x], red[threadIdx.x + w]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) tot[q] = red[0];
+    const int q = blockIdx.x;
+    DD s{0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kBlock) s = dd_add(s, part[(int64_t)b * nv + q]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = dd_add(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
+    if (threadIdx.x == 0) tot[q] = red[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_moments_final(const DD* __restrict__ part, int nb,
-                                                          const double* __restrict__ z,
-                                                          int64_t ld, int64_t n,
-                                                          double* __restrict__ out) {
-    __shared__ DD tot[27];
-    merge_partials<27>(part, nb, tot);
+__global__ void k_moments_final(const DD* __restrict__ tot, const double* __restrict__ z, int64_t ld,
+                                int64_t n, double* __restrict__ out) {
     if (threadIdx.x == 0) {
         const double nd = (double)n;
         for (int j = 0; j < 6; ++j) {
@@ -196,10 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_moments_final(const DD* __restrict__
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_diff2_final(const DD* __restrict__ part, int nb,
-                                                        double* __restrict__ out) {
-    __shared__ DD tot[6];
-    merge_partials<6>(part, nb, tot);
+__global__ void k_diff2_final(const DD* __restrict__ tot, double* __restrict__ out) {
     if (threadIdx.x < 6) out[threadIdx.x] = tot[threadIdx.x].hi + tot[threadIdx.x].lo;
 }
 
@@ -213,7 +247,7 @@ int reduce_grid(int64_t n) {
 }  // namespace
 
 size_t reduce_ws_bytes(int64_t n) {
-    return (size_t)reduce_grid(n) * 27 * sizeof(DD);
+    return ((size_t)reduce_grid(n) + 1) * 27 * sizeof(DD);   // block partials, then the totals
 }
 
 hipError_t launch_moments(const double* z, int64_t n, int64_t ld, double* ws, double* out27,
@@ -224,10 +258,14 @@ hipError_t launch_moments(const double* z, int64_t n, int64_t ld, double* ws, do
     op.ld = ld;
     for (int j = 0; j < 6; ++j) op.sh[j] = 0.0;  // loaded on the device by init()
     DD* part = reinterpret_cast<DD*>(ws);
+    DD* tot = part + (size_t)nb * 27;
     hipLaunchKernelGGL(k_partials<MomentsOp>, dim3(nb), dim3(kBlock), 0, s, op, n, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, s, part, nb, z, ld, n, out27);
+    hipLaunchKernelGGL(k_merge, dim3(27), dim3(kBlock), 0, s, part, nb, 27, tot);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, s, tot, z, ld, n, out27);
     return hipGetLastError();
 }
 
@@ -236,10 +274,14 @@ hipError_t launch_diff2(const double* zs, const double* zf, int64_t n, int64_t l
     const int nb = reduce_grid(n);
     Diff2Op op{zs, zf, ld};
     DD* part = reinterpret_cast<DD*>(ws);
+    DD* tot = part + (size_t)nb * 6;
     hipLaunchKernelGGL(k_partials<Diff2Op>, dim3(nb), dim3(kBlock), 0, s, op, n, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diff2_final, dim3(1), dim3(kBlock), 0, s, part, nb, out6);
+    hipLaunchKernelGGL(k_merge, dim3(6), dim3(kBlock), 0, s, part, nb, 6, tot);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diff2_final, dim3(1), dim3(64), 0, s, tot, out6);
     return hipGetLastError();
 }
 

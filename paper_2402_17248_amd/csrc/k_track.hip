@@ -6,7 +6,7 @@
 // Compiled with -ffp-contract=off: every fused multiply-add is written out
 // as fma(), so the fused and per-element lattice paths execute the same
 // operations in the same order and agree bitwise.
-#include "hbl_internal.hpp"
+#include "hbl_elements.hpp"
 
 namespace hbl {
 namespace {
@@ -33,13 +33,48 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     }
 }
 
+// sin(2 pi u) and cos(2 pi u) for u in [0, 1): the octant reduction
+// u = (k + 1/2)/8 + d is exact for a 53-bit u, theta = 2 pi d lies in
+// [-pi/8, pi/8), sin and cos of theta come from their Taylor series (nested
+// form, truncation below 1e-18) and the octant centre (2k+1) pi/8 enters
+// through the angle-addition formulas.  Error ~2e-16 absolute.
+__device__ __forceinline__ void sincos_2pi(double u, double& s, double& c) {
+    const double k = floor(u * 8.0);
+    const double d = u - (k + 0.5) * 0.125;
+    const double th = d * (2.0 * M_PI);
+    const double t2 = th * th;
+    double ps = fma(-t2, 1.0 / 156.0, 1.0);
+    ps = fma(-t2 * (1.0 / 110.0), ps, 1.0);
+    ps = fma(-t2 * (1.0 / 72.0), ps, 1.0);
+    ps = fma(-t2 * (1.0 / 42.0), ps, 1.0);
+    ps = fma(-t2 * (1.0 / 20.0), ps, 1.0);
+    ps = fma(-t2 * (1.0 / 6.0), ps, 1.0);
+    const double st = th * ps;
+    double pc = fma(-t2, 1.0 / 182.0, 1.0);
+    pc = fma(-t2 * (1.0 / 132.0), pc, 1.0);
+    pc = fma(-t2 * (1.0 / 90.0), pc, 1.0);
+    pc = fma(-t2 * (1.0 / 56.0), pc, 1.0);
+    pc = fma(-t2 * (1.0 / 30.0), pc, 1.0);
+    pc = fma(-t2 * (1.0 / 12.0), pc, 1.0);
+    const double ct = fma(-t2 * 0.5, pc, 1.0);
+    const int ki = (int)k;
+    const double s1 = 0.38268343236508978, c1 = 0.92387953251128674;  // sin, cos of pi/8
+    const bool a = ((ki ^ (ki >> 1)) & 1) == 0;
+    double sp = a ? s1 : c1, cp = a ? c1 : s1;
+    if (ki >= 4) sp = -sp;
+    if ((ki + 2) & 4) cp = -cp;
+    s = fma(sp, ct, cp * st);
+    c = fma(cp, ct, -(sp * st));
+}
+
 struct FillArgs {
     double mean[6];
     double sigma[6];
 };
 
 // One thread per particle.  Pair q of particle g: counter (g_lo, g_hi, q,
-// "GAUS"), two 53-bit uniforms u1 in (0,1], u2 in [0,1), Box-Muller.
+// "GAUS"), two 53-bit uniforms u1 in (0,1], u2 in [0,1), Box-Muller
+// (Box & Muller 1958): r = sqrt(-2 ln u1), (r cos 2 pi u2, r sin 2 pi u2).
 __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z, int64_t n,
                                                           int64_t ld, uint32_t key0,
                                                           uint32_t key1, int64_t i0,
@@ -56,8 +91,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z
             const double u1 = ((double)ua + 1.0) * 0x1.0p-53;
             const double u2 = (double)ub * 0x1.0p-53;
             const double r = sqrt(-2.0 * log(u1));
-            const double ang = 2.0 * M_PI * u2;
-            const double cs = cos(ang), sn = sin(ang);
+            double sn, cs;
+            sincos_2pi(u2, sn, cs);
             z[(2 * q) * ld + i] = a.mean[2 * q] + a.sigma[2 * q] * (r * cs);
             z[(2 * q + 1) * ld + i] = a.mean[2 * q + 1] + a.sigma[2 * q + 1] * (r * sn);
         }
@@ -65,56 +100,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z
 }
 
 // --------------------------------------------------------------- lattice
-struct P6 {
-    double x, y, t, px, py, pt;
-};
-
-__device__ __forceinline__ void el_drift(P6& p, const double* c) {
-    p.x = fma(c[0], p.px, p.x);
-    p.y = fma(c[0], p.py, p.y);
-    p.t = fma(c[1], p.pt, p.t);
-}
-
-__device__ __forceinline__ void el_quad(P6& p, const double* c) {
-    const double x = p.x, px = p.px, y = p.y, py = p.py;
-    p.x = fma(c[1], px, c[0] * x);
-    p.px = fma(c[3], px, c[2] * x);
-    p.y = fma(c[5], py, c[4] * y);
-    p.py = fma(c[7], py, c[6] * y);
-    p.t = fma(c[8], p.pt, p.t);
-}
-
-__device__ __forceinline__ void el_sbend(P6& p, const double* c) {
-    const double x = p.x, px = p.px, pt = p.pt;
-    p.x = fma(c[2], pt, fma(c[1], px, c[0] * x));
-    p.px = fma(c[5], pt, fma(c[4], px, c[3] * x));
-    p.y = fma(c[9], p.py, p.y);
-    p.t = fma(c[8], pt, fma(c[7], px, fma(c[6], x, p.t)));
-}
-
-__device__ __forceinline__ void el_lens(P6& p, const double* c) {
-    p.px = fma(c[0], p.x, p.px);
-    p.py = fma(c[0], p.y, p.py);
-}
-
-__device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {
-    p.x = z[i];
-    p.y = z[ld + i];
-    p.t = z[2 * ld + i];
-    p.px = z[3 * ld + i];
-    p.py = z[4 * ld + i];
-    p.pt = z[5 * ld + i];
-}
-
-__device__ __forceinline__ void store6(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
-    z[i] = p.x;
-    z[ld + i] = p.y;
-    z[2 * ld + i] = p.t;
-    z[3 * ld + i] = p.px;
-    z[4 * ld + i] = p.py;
-    z[5 * ld + i] = p.pt;
-}
-
 // Fused lattice: a grid-stride (persistent) loop over tiles of kPer*kBlock
 // particles; each thread keeps kPer particles in registers through the
 // whole element sequence.  The element kind and coefficients are uniform
@@ -215,15 +200,20 @@ __global__ __launch_bounds__(kBlock) void k_lattice_one(double* __restrict__ z, 
 // r <- r (2 - a r) (the relative change per substep is small, checked by the
 // host); NEWTON == 0 divides every substep.  gmid[n] = gamma_ref at the
 // middle of substep n (uniform across the wavefront: scalar loads).
+// The transport gap before the stage (pre) and after it (post) are applied
+// in registers in the same pass (empty sequences for a lone stage), and the
+// recorded training input is the state after `pre`.
 template <int NEWTON>
 __global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_t n, int64_t ld,
                                                   double* __restrict__ rec, int64_t rld,
                                                   StageParams sp,
-                                                  const double* __restrict__ gmid) {
+                                                  const double* __restrict__ gmid,
+                                                  LatticeView pre, LatticeView post) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
         P6 p;
         load6(z, ld, i, p);
+        apply_elements(p, pre);
         if (rec) store6(rec, rld, i, p);
         const double dg = -p.pt * sp.bg_in;
         const double hb = sp.h * sp.bg_in;
@@ -259,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_
         p.py = vy * sp.inv_h_bgout;
         p.t = fma(sp.r56, p.pt, p.t);
         p.pt = p.pt * sp.pt_scale;
+        apply_elements(p, post);
         store6(z, ld, i, p);
     }
 }
@@ -319,26 +310,21 @@ hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind
 }
 
 hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
-                        const StageParams& p, const double* gmid, hipStream_t s) {
+                        const StageParams& p, const double* gmid, const LatticeView& pre,
+                        const LatticeView& post, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int grid = grid_for(n, kBlock, 1 << 20);
+#define HBL_STAGE_LAUNCH(K)                                                                        \
+    hipLaunchKernelGGL(k_stage<K>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid, pre, \
+                       post)
     switch (p.newton) {
-        case 1:
-            hipLaunchKernelGGL(k_stage<1>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
-            break;
-        case 2:
-            hipLaunchKernelGGL(k_stage<2>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
-            break;
-        case 3:
-            hipLaunchKernelGGL(k_stage<3>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
-            break;
-        case 4:
-            hipLaunchKernelGGL(k_stage<4>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
-            break;
-        default:
-            hipLaunchKernelGGL(k_stage<0>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid);
-            break;
+        case 1: HBL_STAGE_LAUNCH(1); break;
+        case 2: HBL_STAGE_LAUNCH(2); break;
+        case 3: HBL_STAGE_LAUNCH(3); break;
+        case 4: HBL_STAGE_LAUNCH(4); break;
+        default: HBL_STAGE_LAUNCH(0); break;
     }
+#undef HBL_STAGE_LAUNCH
     return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ def _load():
         "hbl_lattice_info": ([vp, dp, C.POINTER(i32)], st),
         "hbl_push_lattice": ([vp, i64, i64, vp, C.POINTER(Ref), C.c_uint32, vp], st),
         "hbl_apply_stage": ([vp, i64, i64, C.POINTER(Element), C.POINTER(Ref), vp, i64, vp], st),
+        "hbl_apply_stage_gaps": ([vp, i64, i64, vp, C.POINTER(Element), vp, C.POINTER(Ref), vp, i64, vp], st),
         "hbl_moments": ([vp, i64, i64, dp, dp, vp], st),
         "hbl_moments_async": ([vp, i64, i64, vp, vp], st),
         "hbl_emittances": ([dp, dp], st),
@@ -91,6 +92,7 @@ def _load():
         "hbl_surrogate_loss_grad": ([vp, vp, vp, i64, C.POINTER(C.c_int32), i32, C.POINTER(C.c_float),
                                      dp, vp], st),
         "hbl_surrogate_apply": ([vp, i64, i64, vp, C.POINTER(Ref), vp], st),
+        "hbl_surrogate_apply_gaps": ([vp, i64, i64, vp, vp, vp, C.POINTER(Ref), vp], st),
         "hbl_surrogate_save": ([vp, C.c_char_p], st),
         "hbl_surrogate_load": ([C.c_char_p, C.POINTER(vp)], st),
     }
@@ -190,13 +192,18 @@ class Lattice:
             pass
 
 
-def apply_stage(z, stage, ref: Ref, record=None, n=None, stream=None):
+def apply_stage(z, stage, ref: Ref, record=None, n=None, stream=None, pre=None, post=None):
+    """Fine-step stage; with pre/post (Lattice) the gaps around it run in the same pass."""
     ptr, n, ld = _bunch_args(z, n)
     el = stage if isinstance(stage, Element) else element(stage)
     rp, rld = (None, 0)
     if record is not None:
         rp, _, rld = _bunch_args(record, n)
-    _call("hbl_apply_stage", ptr, n, ld, C.byref(el), C.byref(ref), rp, rld, stream or current_stream())
+    if pre is None and post is None:
+        _call("hbl_apply_stage", ptr, n, ld, C.byref(el), C.byref(ref), rp, rld, stream or current_stream())
+    else:
+        _call("hbl_apply_stage_gaps", ptr, n, ld, pre._h if pre else None, C.byref(el),
+              post._h if post else None, C.byref(ref), rp, rld, stream or current_stream())
 
 
 def moments(z, n=None, stream=None):
@@ -299,10 +306,16 @@ class Surrogate:
               len(idx), g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), stream or current_stream())
         return loss.value, g
 
-    def apply(self, z, ref: Optional[Ref] = None, n=None, stream=None):
+    def apply(self, z, ref: Optional[Ref] = None, n=None, stream=None, pre=None, post=None):
+        """Inference in place; with pre/post (Lattice) the gaps around the stage run in the same pass."""
         ptr, n, ld = _bunch_args(z, n)
-        _call("hbl_surrogate_apply", ptr, n, ld, self._h, C.byref(ref) if ref is not None else None,
-              stream or current_stream())
+        if pre is None and post is None:
+            _call("hbl_surrogate_apply", ptr, n, ld, self._h, C.byref(ref) if ref is not None else None,
+                  stream or current_stream())
+        else:
+            _call("hbl_surrogate_apply_gaps", ptr, n, ld, pre._h if pre else None, self._h,
+                  post._h if post else None, C.byref(ref) if ref is not None else None,
+                  stream or current_stream())
 
     def close(self):
         if getattr(self, "_h", None):

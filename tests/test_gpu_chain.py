@@ -1,7 +1,8 @@
 """GPU parity of the staged beamline (§4, Fig. 1: stages joined by transport
 gaps): the fine-step chain against the oracle chain on sampled particles,
-and the surrogate chain against the oracle evaluating the same trained
-networks in its bf16-emulation mode."""
+and the surrogate chain against the oracle evaluating the same networks (set
+from oracle-made parameters) in its bf16-emulation mode.  The sampled
+particles start from the oracle's fill of the same seed and indices."""
 import numpy as np
 import pytest
 
@@ -19,68 +20,140 @@ def hbl():
 
 def sample(z, idx):
     torch = __import__("torch")
+    torch.cuda.synchronize()
     return np.ascontiguousarray(z[:, torch.from_numpy(idx).cuda()].cpu().numpy())
 
 
-def test_fine_step_chain_parity(hbl, orc):
-    from paper_2402_17248_amd.chain import Chain
-    n = 200_001
-    wl = W.c5_chain(n=n, nsub=500)
-    chain = Chain(wl.beamline, wl.E_MeV)
-    assert chain.stage_count == 4 and chain.n_elements() == 5 + 3 * 12 + 5 + 4
+def sample_idx(n, m, seed):
+    idx = np.sort(np.random.default_rng(seed).choice(n, m, replace=False))
+    idx[0], idx[-1] = 0, n - 1
+    return idx
+
+
+def seed_bunch(hbl, wl, n, idx, orc):
+    """The bunch the benchmark tracks (the library's fill), with the sampled
+    particles replaced by the oracle's fill of the same indices, so that both
+    sides track identical bytes there (the fills agree to ~1e-15 sigma, which the
+    mismatched chain would amplify; the fill has its own parity test)."""
+    torch = __import__("torch")
     z = hbl.new_bunch(n)
     hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
-    idx = np.sort(np.random.default_rng(9).choice(n, 1500, replace=False))
-    idx[-1] = n - 1
-    c = sample(z, idx)
+    c = orc.fill_gaussian(0, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, idx=idx)
+    z[:, torch.from_numpy(idx).cuda()] = torch.from_numpy(c).cuda()
+    return z, c
+
+
+def track_with_path_scale(orc, c, beamline, oref):
+    """Oracle tracking element by element, returning per coordinate and
+    particle the largest magnitude the coordinate took at an element boundary.
+    Across four stages a one-ulp change of the input moves a coordinate by up
+    to ~3e-12 of the beam's rms at the end (mismatch oscillations inside the
+    stages, cancellation in the chicanes), but by < 5e-13 of this scale."""
+    scale = np.abs(c).copy()
+    for seg in beamline:
+        for el in (seg if isinstance(seg, list) else [seg]):
+            orc.push(c, [el], oref)
+            np.maximum(scale, np.abs(c), out=scale)
+    return scale
+
+
+@pytest.mark.parametrize("n,nsub", [(200_001, 500), (25_000_000, 2000)])
+def test_fine_step_chain_parity(hbl, orc, n, nsub):
+    """Four stages, gaps fused into the stage kernels, at a small size and at
+    the benchmark's full size and substep count (sampled particles): 1e-12
+    relative to the largest magnitude of the coordinate along the path."""
+    from paper_2402_17248_amd.chain import Chain
+    wl = W.c5_chain(n=n, nsub=nsub)
+    chain = Chain(wl.beamline, wl.E_MeV)
+    assert chain.stage_count == 4 and chain.n_elements() == 5 + 3 * 15 + 5 + 4
+    idx = sample_idx(n, 1000, 9)
+    z, c = seed_bunch(hbl, wl, n, idx, orc)
     ref = chain.run(z, n=n)
     g = sample(z, idx)
     oref = orc.Ref.from_energy(wl.E_MeV)
-    orc.track(c, wl.beamline, oref)
-    assert rel_err(g, c).max() < 1e-12
+    scale = track_with_path_scale(orc, c, wl.beamline, oref)
     assert abs(ref.gamma / oref.gamma - 1) < 1e-15 and abs(ref.s - oref.s) < 1e-12
+    rms = np.sqrt(np.mean(c * c, axis=1))[:, None]
+    err = np.abs(g - c)
+    path = (err / np.maximum(scale, rms)).max(axis=1)
+    plain = (err / np.maximum(np.abs(c), rms)).max(axis=1)
+    print("path-relative", path, "plain", plain)
+    assert path.max() < 1e-12, (path, plain)
 
 
-def test_surrogate_chain_parity_and_reference(hbl, orc):
-    """Two stages, small training: the point is that the chain composes the
-    library calls exactly as the oracle composes its own."""
-    from paper_2402_17248_amd.chain import Chain
-    n = 50_000
-    wl = W.c5_chain(n=n, nsub=300, n_stages=2)
-    chain = Chain(wl.beamline, wl.E_MeV)
-    chain.train_surrogates(1 << 14, wl.bunch.sigma, W.c5_pair_seed, W.mlp_init_seed, W.shuffle_seed,
-                           epochs=3, batch=1024, lr=1e-3, lr_final=1e-4)
-    z = hbl.new_bunch(n)
-    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
-    idx = np.sort(np.random.default_rng(10).choice(n, 1000, replace=False))
-    c = sample(z, idx)
-    ref = chain.run(z, n=n, use_surrogates=True)
-    g = sample(z, idx)
-    # oracle: lattice gaps by the oracle, stages by the oracle's bf16-emulation network
+def oracle_surrogates(hbl, orc, wl, chain, seed0):
+    """Per stage: oracle-made parameters (initialisation + a perturbation) and
+    the oracle's normalisation of oracle-tracked stage pairs."""
+    m = 4096
+    c = orc.fill_gaussian(m, 500 + seed0, (0.0,) * 6, wl.bunch.sigma)
+    oref = orc.Ref.from_energy(wl.E_MeV)
+    out, k = [], 0
+    for seg in wl.beamline:
+        if isinstance(seg, list):
+            orc.push(c, seg, oref)
+            continue
+        xin = c.copy()
+        orc.push(c, [seg], oref)
+        norm = orc.norm_stats(xin, c, m)
+        p = orc.mlp_init(orc.shape(), seed0 + k)
+        p = (p + 0.05 * np.random.default_rng(seed0 + k).standard_normal(p.shape)).astype(np.float32)
+        sur = hbl.Surrogate(0)
+        sur.set_params(p)
+        sur.set_norm(norm)
+        sur.set_stage(chain.stage(k), chain.entry_ref(k))
+        chain.surrogates[k] = sur
+        out.append((p, norm))
+        k += 1
+    return out
+
+
+def oracle_surrogate_chain(orc, wl, nets, c):
     oref = orc.Ref.from_energy(wl.E_MeV)
     k = 0
     for seg in wl.beamline:
         if isinstance(seg, list):
             orc.push(c, seg, oref)
         else:
-            s = chain.surrogates[k]
-            c = orc.mlp_apply(orc.shape(), s.get_params(), np.array(s.get_norm()), c, mode=1)
+            p, norm = nets[k]
+            c = orc.mlp_apply(orc.shape(), p, norm, c, mode=1)
             oref.gamma += seg.dE_MeV / oref.mass_MeV
             oref.s += seg.L
             k += 1
-    assert abs(ref.gamma / oref.gamma - 1) < 1e-15
-    # two bf16 networks in sequence: rounding-boundary flips (see test_gpu_surrogate)
-    # move a few percent of the particles; the lattice between them is exact
+    return c, oref
+
+
+@pytest.mark.parametrize("n,n_stages", [(50_001, 2), (25_000_000, 4)])
+def test_surrogate_chain_parity(hbl, orc, n, n_stages):
+    """The chain composes lattice gaps and surrogate inference exactly as the
+    oracle composes its own, small and at the benchmark's full size."""
+    from paper_2402_17248_amd.chain import Chain
+    wl = W.c5_chain(n=n, nsub=300, n_stages=n_stages)
+    chain = Chain(wl.beamline, wl.E_MeV)
+    nets = oracle_surrogates(hbl, orc, wl, chain, 40)
+    idx = sample_idx(n, 1000, 10)
+    z, c = seed_bunch(hbl, wl, n, idx, orc)
+    ref = chain.run(z, n=n, use_surrogates=True)
+    g = sample(z, idx)
+    c, oref = oracle_surrogate_chain(orc, wl, nets, c)
+    assert abs(ref.gamma / oref.gamma - 1) < 1e-15 and abs(ref.s - oref.s) < 1e-12
+    # bf16 networks in sequence: rounding-boundary flips (see test_gpu_surrogate)
+    # move ~2 % of the particles per network; the lattices between them are exact
     sd = np.sqrt(np.mean(c * c, axis=1))[:, None]
     d = np.abs(g - c) / sd
-    assert np.median(d) < 1e-5
-    assert np.mean(d.max(axis=0) > 1e-3) < 0.1
-    assert d.max() < 0.2
+    moved = np.mean(d.max(axis=0) > 1e-3)
+    assert np.median(d) < 1e-5, np.median(d)
+    assert moved < 0.05 * n_stages, moved
+    assert d.max() < 0.1 * n_stages, d.max()
 
 
 def test_pairs_record_stage_input(hbl, orc):
+    """Training pairs of stage 2: the recorded input is the bunch at the stage
+    entrance (after T, S1 and the interstage), the output the bunch after it.
+    The library fills the pair bunch itself (fill parity ~1e-15 sigma); the
+    imaging interstage forms the entrance coordinates by cancellation of terms
+    ~1e3 times larger, hence the path-relative bound."""
     from paper_2402_17248_amd.chain import Chain
-    wl = W.c5_chain(n=10, nsub=100)
+    wl = W.c5_chain(n=10, nsub=500)
     chain = Chain(wl.beamline, wl.E_MeV)
     n = 4099
     zin, zout = chain.make_pairs(1, n, 77, wl.bunch.sigma)
@@ -90,10 +163,69 @@ def test_pairs_record_stage_input(hbl, orc):
     b = np.ascontiguousarray(zout[:, :n].cpu().numpy())
     c = orc.fill_gaussian(n, 77, (0.0,) * 6, wl.bunch.sigma)
     oref = orc.Ref.from_energy(wl.E_MeV)
-    # up to stage 2's entrance: T, S1, T C
-    orc.track(c, wl.beamline[:3], oref)
-    assert rel_err(a, c).max() < 1e-12
+    scale = track_with_path_scale(orc, c, wl.beamline[:3], oref)
+    rms = np.sqrt(np.mean(c * c, axis=1))[:, None]
+    assert (np.abs(a - c) / np.maximum(scale, rms)).max() < 1e-12
     orc.push(c, [wl.beamline[3]], oref)
-    assert rel_err(b, c).max() < 1e-12
+    np.maximum(scale, np.abs(c), out=scale)
+    rms = np.sqrt(np.mean(c * c, axis=1))[:, None]
+    assert (np.abs(b - c) / np.maximum(scale, rms)).max() < 1e-12
     e = chain.entry_ref(1)
     assert abs(e.gamma - (1000.0 + 10000.0) / hbl.MEC2_MEV) < 1e-9
+    assert abs(e.s - (1.3 + 0.3 + 13.3)) < 1e-12
+
+
+def test_gap_fused_passes_are_bitwise_equal(hbl):
+    """Each stage kernel running its transport gaps in registers gives exactly
+    the bunch of separate lattice + stage calls (the same element code, in
+    the same order), for fine-step stages and for surrogates."""
+    from paper_2402_17248_amd.chain import Chain
+    torch = __import__("torch")
+    n = 30_001
+    wl = W.c5_chain(n=n, nsub=200, n_stages=2)
+    chain = Chain(wl.beamline, wl.E_MeV)
+    z0 = hbl.new_bunch(n)
+    hbl.fill_gaussian(z0, 4, (0.0,) * 6, wl.bunch.sigma, n=n)
+    outs = []
+    for kw in (dict(), dict(gaps_fused=False), dict(fused=False)):
+        z = z0.clone()
+        r = chain.run(z, n=n, **kw)
+        outs.append((z, r.gamma, r.s))
+    torch.cuda.synchronize()
+    for z, g, s in outs[1:]:
+        assert torch.equal(z, outs[0][0]) and g == outs[0][1] and abs(s - outs[0][2]) < 1e-12
+    chain.train_surrogates(1 << 13, wl.bunch.sigma, W.c5_pair_seed, W.mlp_init_seed, W.shuffle_seed,
+                           epochs=1, batch=512)
+    za, zb = z0.clone(), z0.clone()
+    ra = chain.run(za, n=n, use_surrogates=True)
+    rb = chain.run(zb, n=n, use_surrogates=True, gaps_fused=False)
+    torch.cuda.synchronize()
+    assert torch.equal(za, zb) and ra.gamma == rb.gamma
+    # recorded pairs: the stage input after its entrance gap
+    ia, oa = chain.make_pairs(1, 4096, 12, wl.bunch.sigma)
+    zin = hbl.new_bunch(4096)
+    zo = hbl.new_bunch(4096)
+    hbl.fill_gaussian(zo, 12, (0.0,) * 6, wl.bunch.sigma, n=4096)
+    chain.run(zo, n=4096, stop_before_stage=1, record=zin, gaps_fused=False)
+    torch.cuda.synchronize()
+    assert torch.equal(ia[:, :4096], zin[:, :4096]) and torch.equal(oa[:, :4096], zo[:, :4096])
+
+
+def test_gap_lattice_energy_checked(hbl):
+    """A gap lattice compiled for another reference energy is rejected before
+    any launch, and the rejected call leaves the reference unchanged."""
+    wl = W.c5_chain(n=10, nsub=50, n_stages=2)
+    z = hbl.new_bunch(128)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    wrong = hbl.Lattice(W.triplet(), hbl.Ref.from_energy(2 * wl.E_MeV))
+    st = hbl.element(wl.beamline[1])
+    with pytest.raises(hbl.HblError, match="compiled for gamma"):
+        hbl.apply_stage(z, st, ref, n=128, pre=wrong)
+    assert ref.gamma == hbl.Ref.from_energy(wl.E_MeV).gamma and ref.s == 0.0
+    sur = hbl.Surrogate(1)
+    sur.set_norm([0.0] * 6 + [1.0] * 6 + [0.0] * 6 + [1.0] * 6)
+    with pytest.raises(hbl.HblError, match="declared stage"):
+        sur.apply(z, n=128, pre=wrong)
+    sur.set_stage(st, ref)
+    with pytest.raises(hbl.HblError, match="compiled for gamma"):
+        sur.apply(z, ref, n=128, pre=wrong)

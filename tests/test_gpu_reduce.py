@@ -1,12 +1,13 @@
 """GPU parity of the diagnostics reductions (moments, emittances, paired
-metrics) against the oracle's exact sums on the same bunch bytes."""
+metrics) against the oracle's exact sums on the same bunch bytes (bunches
+made by the oracle and uploaded)."""
 import math
 
 import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import to_dev, to_host
+from gpu_util import to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -33,10 +34,9 @@ def moment_errors(orc, g_mean, g_cov, z):
 def test_moments_parity(hbl, orc, n, offset):
     sig = np.array(W.BunchSpec(1, 1).sigma)
     mean = tuple(offset * sig)
-    z = hbl.new_bunch(n)
-    hbl.fill_gaussian(z, 11, mean, tuple(sig), n=n)
+    host = orc.fill_gaussian(n, 11, mean, tuple(sig))
+    z = to_dev(host)
     g_mean, g_cov = hbl.moments(z, n=n)
-    host = to_host(z, n)
     em, ec, oc = moment_errors(orc, g_mean, g_cov, host)
     assert em < 1e-13 and ec < 1e-13, (em, ec)
     # emittance within its conditioning of the exact one
@@ -53,14 +53,29 @@ def test_moments_parity(hbl, orc, n, offset):
 def test_moments_of_correlated_stage_exit(hbl, orc):
     wl = W.c3_stage(n=50_001, nsub=500)
     n = wl.bunch.n
-    z = hbl.new_bunch(n)
-    hbl.fill_gaussian(z, 3, (0.0,) * 6, wl.bunch.sigma, n=n)
-    ref = hbl.Ref.from_energy(wl.E_MeV)
-    hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
-    hbl.apply_stage(z, wl.beamline[1], ref, n=n)
-    g_mean, g_cov = hbl.moments(z, n=n)
-    em, ec, _ = moment_errors(orc, g_mean, g_cov, to_host(z, n))
+    host = orc.fill_gaussian(n, 3, (0.0,) * 6, wl.bunch.sigma)
+    orc.track(host, wl.beamline[:2], orc.Ref.from_energy(wl.E_MeV))
+    g_mean, g_cov = hbl.moments(to_dev(host), n=n)
+    em, ec, _ = moment_errors(orc, g_mean, g_cov, host)
     assert em < 1e-13 and ec < 1e-13
+
+
+def test_moments_full_size_tiled(hbl, orc):
+    """At the benchmark size (2.5e7, the launch shape the chain step uses):
+    a bunch made of 25 copies of a 1e6-particle oracle bunch has that bunch's
+    mean and covariance."""
+    torch = __import__("torch")
+    m, reps = 1_000_000, 25
+    host = orc.fill_gaussian(m, 21, (0.0,) * 6, W.BunchSpec(1, 1).sigma)
+    orc.track(host, [W.triplet()], orc.Ref.from_energy(1000.0))
+    z = torch.from_numpy(host).cuda().repeat(1, reps).contiguous()
+    g_mean, g_cov = hbl.moments(z, n=m * reps)
+    em, ec, _ = moment_errors(orc, g_mean, g_cov, host)
+    assert em < 1e-13 and ec < 1e-13, (em, ec)
+    out = torch.empty(27, dtype=torch.float64, device="cuda")
+    hbl.moments_async(z, out, n=m * reps)
+    torch.cuda.synchronize()
+    assert out.cpu().tolist() == g_mean + g_cov
 
 
 def test_moments_deterministic(hbl):
@@ -85,12 +100,10 @@ def test_nonfinite_detected(hbl):
 def test_compare_parity(hbl, orc):
     n = 20_001
     sig = W.BunchSpec(1, 1).sigma
-    f = hbl.new_bunch(n)
-    hbl.fill_gaussian(f, 8, (0.0,) * 6, sig, n=n)
-    s = f.clone()
-    s[:, :n] = s[:, :n] * 1.001 + 1e-9
-    r, c, e = hbl.compare(s, f, n=n)
-    ro, co, eo = orc.compare(to_host(s, n), to_host(f, n))
+    fh = orc.fill_gaussian(n, 8, (0.0,) * 6, sig)
+    sh = fh * 1.001 + 1e-9
+    r, c, e = hbl.compare(to_dev(sh), to_dev(fh), n=n)
+    ro, co, eo = orc.compare(sh, fh)
     assert np.abs(np.array(r) - ro).max() < 1e-12 * np.abs(ro).max()
     assert np.abs(np.array(c) - co).max() < 1e-12 + 1e-10 * np.abs(co).max()
     assert np.abs(np.array(e) - eo).max() < 1e-10

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import to_host
+from gpu_util import to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -27,18 +27,20 @@ def hbl():
 
 
 @pytest.fixture(scope="module")
-def pairs(hbl):
-    """2^14 stage pairs: triplet, then the fine-step stage with its input recorded."""
+def pairs(hbl, orc):
+    """2^14 stage pairs made by the oracle (triplet, then the fine-step stage,
+    its input kept) and uploaded: (n, inputs on device, outputs on device,
+    inputs on host, outputs on host, stage, reference at the stage entrance)."""
     n = 1 << 14
     wl = W.c3_stage(n=n, nsub=400)
-    z = hbl.new_bunch(n)
-    hbl.fill_gaussian(z, 3, (0.0,) * 6, wl.bunch.sigma, n=n)
-    ref = hbl.Ref.from_energy(wl.E_MeV)
-    hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
-    rec = hbl.new_bunch(n)
-    entry = ref.copy()
-    hbl.apply_stage(z, wl.beamline[1], ref, record=rec, n=n)
-    return n, rec, z, to_host(rec, n), to_host(z, n), wl.beamline[1], entry
+    c = orc.fill_gaussian(n, 3, (0.0,) * 6, wl.bunch.sigma)
+    oref = orc.Ref.from_energy(wl.E_MeV)
+    orc.push(c, wl.beamline[0], oref)
+    xin = c.copy()
+    orc.push(c, [wl.beamline[1]], oref)
+    entry = hbl.Ref.from_energy(wl.E_MeV)
+    entry.s = oref.s - wl.beamline[1].L
+    return n, to_dev(xin), to_dev(c), xin, c, wl.beamline[1], entry
 
 
 def perturbed(orc, seed):
@@ -98,12 +100,13 @@ def test_forward_full_size_sampled(hbl, orc, pairs):
     s.set_norm(norm)
     N = W.C4_INFER_N
     z = hbl.new_bunch(N)
-    hbl.fill_gaussian(z, W.C4_INFER_SEED, tuple(norm[0:6]), tuple(norm[6:12]), n=N)
+    mean, sd = tuple(norm[0:6]), tuple(norm[6:12])
+    hbl.fill_gaussian(z, W.C4_INFER_SEED, mean, sd, n=N)
     torch = __import__("torch")
     idx = np.sort(np.random.default_rng(3).choice(N, 2000, replace=False))
     idx[-1] = N - 1
     ti = torch.from_numpy(idx).cuda()
-    x0 = np.ascontiguousarray(z[:, ti].cpu().numpy())
+    x0 = orc.fill_gaussian(0, W.C4_INFER_SEED, mean, sd, idx=idx)   # same particles, the oracle's fill
     s.apply(z, n=N)
     g = np.ascontiguousarray(z[:, ti].cpu().numpy())
     c = orc.mlp_apply(orc.shape(), p, norm, x0, mode=1)
@@ -142,25 +145,30 @@ def test_first_adam_step_and_epoch_order(hbl, orc, pairs):
     gradient of the first batch of the oracle's epoch-0 Fisher-Yates order."""
     n, rec, out, xin, xout, _, _ = pairs
     s = hbl.Surrogate(11)
-    p0 = s.get_params()
+    p0 = orc.mlp_init(orc.shape(), 11)
+    assert np.array_equal(s.get_params(), p0.astype(np.float32))
     s.train(rec, out, n, batch=64, epochs=1, lr=1e-3, train_frac=0.7, shuffle_seed=77, max_steps=1)
-    p1 = s.get_params()
+    p1 = s.get_params().astype(np.float64)
     ntr = int(round(0.7 * n))
-    first = orc.epoch_perm(ntr, 77, 0)[:64].astype(np.int32)
-    ref = hbl.Surrogate(11)
-    ref.set_norm(s.get_norm())
-    _, g = ref.loss_grad(rec, out, first)
-    want, _, _ = orc.adam_step(p0, np.zeros(len(p0)), np.zeros(len(p0)), g.astype(np.float64), 1, lr=1e-3)
-    assert np.abs(p1 - want).max() < 1e-6
     # the training normalisation is the oracle's over the training split
     on = orc.norm_stats(xin, xout, ntr)
     assert np.allclose(s.get_norm(), on, rtol=1e-13, atol=0)
+    first = orc.epoch_perm(ntr, 77, 0)[:64]
+    _, g = orc.mlp_loss_grad(orc.shape(), p0, on, xin, xout, first.astype(np.int64), mode=1)
+    want, _, _ = orc.adam_step(p0, np.zeros(len(p0)), np.zeros(len(p0)), g, 1, lr=1e-3)
+    # Adam's first step moves a parameter by lr g / (|g| + eps), i.e. lr sign(g) unless
+    # |g| is ~eps: another batch would change most signs; the bf16 rounding points
+    # of the two sides may flip a few near-zero gradients
+    d = np.abs(p1 - want)
+    assert np.mean(d > 1e-6) < 0.01, np.mean(d > 1e-6)
+    assert d.max() <= 2e-3 + 1e-6
 
 
 def test_training_curve_matches_oracle(hbl, orc, pairs):
     n, rec, out, xin, xout, _, _ = pairs
     s = hbl.Surrogate(12)
-    p0 = s.get_params()
+    p0 = orc.mlp_init(orc.shape(), 12)
+    assert np.array_equal(s.get_params(), p0.astype(np.float32))
     log = s.train(rec, out, n, batch=256, epochs=3, lr=3e-3, lr_final=3e-4, shuffle_seed=5)
     _, _, olog = orc.mlp_train(orc.shape(), p0, xin, xout, batch=256, epochs=3, lr=3e-3, lr_final=3e-4,
                                shuffle_seed=5, mode=1)

@@ -1,7 +1,8 @@
 """GPU parity of the tracking path (fill, lattice, stage) against the CPU
 oracle, through the C ABI.  Tolerance: 1e-12 relative per coordinate
-(max_i |g - c| / max(|c|, rms(c))), oracle started from the GPU's own input
-bytes."""
+(max_i |g - c| / max(|c|, rms(c))).  The fill is compared with the oracle's
+fill from the same seed; the tracking tests start both sides from the
+oracle's fill, uploaded."""
 import numpy as np
 import pytest
 
@@ -52,9 +53,9 @@ def test_fill_full_size_sampled(hbl, orc):
 
 
 def fill_pair(hbl, orc, n, seed):
-    z = hbl.new_bunch(n)
-    hbl.fill_gaussian(z, seed, (0.0,) * 6, sig(), n=n)
-    return z, to_host(z, n)
+    """The oracle's seeded bunch, on the host and uploaded to the device."""
+    c = orc.fill_gaussian(n, seed, (0.0,) * 6, sig())
+    return to_dev(c), c
 
 
 @pytest.mark.parametrize("n", [1, 63, 10_000, 10_001])

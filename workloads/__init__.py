@@ -91,6 +91,24 @@ def triplet() -> List[Element]:
     return [quad(0.3, +2.0), drift(0.2), quad(0.3, -2.0), drift(0.2), quad(0.3, +2.0)]
 
 
+# Interstage triplet strengths (m^-2): with the drifts of interstage(), the
+# gap from one stage's exit to the next stage's entrance images point to point
+# in both planes (R12 = R34 = 0 to ~1e-9 m) with magnification -1, so the beam
+# leaving a stage enters the next one with the same size and divergence.
+INTERSTAGE_K_OUTER = 2.366855065
+INTERSTAGE_K_INNER = 4.411922003
+
+
+def interstage() -> List[Element]:
+    """Gap between two stages: D 6.0, triplet Q(+k_o) D0.2 Q(-k_i) D0.2 Q(+k_o)
+    (quads 0.3 m), D 0.5, four-dipole chicane (5 m), D 0.5 -- 13.3 m, 15
+    elements, mirror-symmetric about the triplet centre (chicane taken as a
+    drift transversely)."""
+    ko, ki = INTERSTAGE_K_OUTER, INTERSTAGE_K_INNER
+    return ([drift(6.0), quad(0.3, +ko), drift(0.2), quad(0.3, -ki), drift(0.2), quad(0.3, +ko),
+             drift(0.5)] + chicane() + [drift(0.5)])
+
+
 def plasma_stage(dE_MeV=9000.0, nsub=2000) -> Stage:
     """0.3 m stage at n0 = 1e17 cm^-3 = 1e23 m^-3."""
     return Stage(L=0.3, n0_m3=1e23, dE_MeV=dE_MeV, nsub=nsub)
@@ -134,13 +152,15 @@ C4_INFER_N = 10_000_000
 
 
 def c5_chain(n=25_000_000, seed=5, nsub=2000, n_stages=4) -> Workload:
-    """[T] S1 [T C] S2 [T C] S3 [T C] S4 [T]; stage k runs 1+10(k-1) -> 11+10(k-1) GeV."""
+    """[T] S1 [I] S2 [I] S3 [I] S4 [T]: T the matching triplet of the single
+    stage, I the imaging interstage (triplet + chicane); stage k runs
+    1+10(k-1) -> 11+10(k-1) GeV."""
     bl: list = [triplet()]
     for k in range(n_stages):
         bl.append(plasma_stage(10_000.0, nsub))
-        bl.append(triplet() + chicane() if k < n_stages - 1 else triplet())
+        bl.append(interstage() if k < n_stages - 1 else triplet())
     return Workload("chain4_2.5e7", BunchSpec(n, seed), E0_MeV, bl,
-                    "4 plasma stages (+10 GeV each) with triplet+chicane gaps")
+                    "4 plasma stages (+10 GeV each) joined by imaging triplet+chicane interstages")
 
 
 def c5_pair_seed(k: int) -> int:
