@@ -173,6 +173,34 @@ double th_minus_sin(double th) {
 
 // Element -> coefficients (first-order map of the linearised equations of
 // motion over the element, for a reference of Lorentz factor gamma).
+}  // namespace
+
+GenCoef hbl::unify(int32_t kind, const ElemCoef& e) {
+    GenCoef u;
+    memset(&u, 0, sizeof u);
+    double* g = u.g;
+    const double* c = e.c;
+    switch (kind) {
+        case kDrift:  // x + L px, y + L py, t + r56 pt
+            g[0] = 1.0; g[1] = c[0]; g[4] = 1.0; g[6] = 1.0; g[7] = c[0]; g[9] = 1.0; g[12] = c[1];
+            break;
+        case kQuad:
+            g[0] = c[0]; g[1] = c[1]; g[3] = c[2]; g[4] = c[3];
+            g[6] = c[4]; g[7] = c[5]; g[8] = c[6]; g[9] = c[7]; g[12] = c[8];
+            break;
+        case kSbend:
+            g[0] = c[0]; g[1] = c[1]; g[2] = c[2]; g[3] = c[3]; g[4] = c[4]; g[5] = c[5];
+            g[6] = 1.0; g[7] = c[9]; g[9] = 1.0; g[10] = c[6]; g[11] = c[7]; g[12] = c[8];
+            break;
+        default:      // thin lens: px + c0 x, py + c0 y
+            g[0] = 1.0; g[3] = c[0]; g[4] = 1.0; g[6] = 1.0; g[8] = c[0]; g[9] = 1.0;
+            break;
+    }
+    return u;
+}
+
+namespace {
+
 hbl_status compile_element(const hbl_element& e, double gamma, int32_t* kind, ElemCoef* c) {
     memset(c, 0, sizeof *c);
     const double bg = sqrt(gamma * gamma - 1.0), beta = bg / gamma;
@@ -249,7 +277,8 @@ struct hbl_lattice {
     double gamma;
     double length;
     int32_t* d_kinds;
-    double* d_coef;
+    double* d_coef;   // one allocation: n GenCoef records, then n ElemCoef records
+    double* d_gen;
     std::vector<int32_t> kinds;
     std::vector<ElemCoef> coef;
 };
@@ -304,6 +333,7 @@ hbl_status hbl_lattice_create(const hbl_element* elems, int32_t n_elem, const hb
     lat->coef = coef;
     lat->d_kinds = nullptr;
     lat->d_coef = nullptr;
+    lat->d_gen = nullptr;
     if (hipGetDevice(&lat->device) != hipSuccess) {
         delete lat;
         set_error(HBL_EHIP, "lattice_create: no HIP device");
@@ -311,17 +341,22 @@ hbl_status hbl_lattice_create(const hbl_element* elems, int32_t n_elem, const hb
     }
     if (n_elem > 0) {
         void *pk = nullptr, *pc = nullptr;
+        std::vector<GenCoef> gen((size_t)n_elem);
+        for (int32_t i = 0; i < n_elem; ++i) gen[i] = unify(kinds[i], coef[i]);
+        const size_t gen_bytes = sizeof(GenCoef) * n_elem;
         if (hipMalloc(&pk, sizeof(int32_t) * n_elem) != hipSuccess ||
-            hipMalloc(&pc, sizeof(ElemCoef) * n_elem) != hipSuccess) {
+            hipMalloc(&pc, gen_bytes + sizeof(ElemCoef) * n_elem) != hipSuccess) {
             if (pk) (void)hipFree(pk);
             delete lat;
             set_error(HBL_ENOMEM, "lattice_create: device allocation failed");
             return HBL_ENOMEM;
         }
         lat->d_kinds = static_cast<int32_t*>(pk);
-        lat->d_coef = static_cast<double*>(pc);
+        lat->d_gen = static_cast<double*>(pc);
+        lat->d_coef = lat->d_gen + (size_t)kGen * n_elem;
         if (hipMemcpy(pk, kinds.data(), sizeof(int32_t) * n_elem, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(pc, coef.data(), sizeof(ElemCoef) * n_elem, hipMemcpyHostToDevice) != hipSuccess) {
+            hipMemcpy(lat->d_gen, gen.data(), gen_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(lat->d_coef, coef.data(), sizeof(ElemCoef) * n_elem, hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipFree(pk);
             (void)hipFree(pc);
             delete lat;
@@ -337,7 +372,7 @@ hbl_status hbl_lattice_destroy(hbl_lattice* lat) {
     clear_error();
     if (!lat) return HBL_OK;
     if (lat->d_kinds) (void)hipFree(lat->d_kinds);
-    if (lat->d_coef) (void)hipFree(lat->d_coef);
+    if (lat->d_gen) (void)hipFree(lat->d_gen);   // holds the ElemCoef records too
     delete lat;
     return HBL_OK;
 }
@@ -363,7 +398,7 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
     if (n > 0 && lat->n_elem > 0) {
         hipStream_t s = (hipStream_t)stream;
         if (flags == HBL_FUSED) {
-            HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_kinds, lat->d_coef, lat->n_elem, s));
+            HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_gen, lat->n_elem, s));
         } else {
             for (int32_t i = 0; i < lat->n_elem; ++i)
                 HBL_HIP(launch_lattice_element(z, n, ld, lat->kinds[i], lat->coef[i], s));
@@ -378,10 +413,11 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
 namespace {
 
 LatticeView view_of(const hbl_lattice* lat) {
-    LatticeView v{nullptr, nullptr, 0};
+    LatticeView v{nullptr, nullptr, nullptr, 0};
     if (lat) {
         v.kinds = lat->d_kinds;
         v.coef = lat->d_coef;
+        v.gen = lat->d_gen;
         v.n = lat->n_elem;
     }
     return v;

@@ -36,30 +36,35 @@ __device__ __forceinline__ void el_sbend(P6& p, const double* c) {
     p.t = fma(c[8], pt, fma(c[7], px, fma(c[6], x, p.t)));
 }
 
+// A thin lens adds the rounded kick: px + round(c0 x), as the unified map does.
 __device__ __forceinline__ void el_lens(P6& p, const double* c) {
-    p.px = fma(c[0], p.x, p.px);
-    p.py = fma(c[0], p.y, p.py);
+    p.px = p.px + c[0] * p.x;
+    p.py = p.py + c[0] * p.y;
 }
 
-// A compiled element sequence (device coefficient table), passed by value.
+// Any element through its unified record (GenCoef): branch-free, bitwise
+// equal to the specialised map of its kind.
+__device__ __forceinline__ void el_unified(P6& p, const double* g) {
+    const double x = p.x, px = p.px, y = p.y, py = p.py, pt = p.pt;
+    p.x = fma(g[2], pt, fma(g[1], px, g[0] * x));
+    p.px = fma(g[5], pt, fma(g[4], px, g[3] * x));
+    p.y = fma(g[7], py, g[6] * y);
+    p.py = fma(g[9], py, g[8] * y);
+    p.t = fma(g[12], pt, fma(g[11], px, fma(g[10], x, p.t)));
+}
+
+// A compiled element sequence (device coefficient tables), passed by value.
 struct LatticeView {
     const int32_t* kinds;
-    const double* coef;
+    const double* coef;   // ElemCoef records
+    const double* gen;    // GenCoef records
     int32_t n;
 };
 
-// Apply the sequence to one particle; the kind and coefficients are uniform
-// across the wavefront (scalar loads, scalar branch).
+// Apply the sequence to one particle: the unified record of each element,
+// read by scalar loads (uniform across the wavefront), no branches.
 __device__ __forceinline__ void apply_elements(P6& p, const LatticeView& lv) {
-    for (int32_t e = 0; e < lv.n; ++e) {
-        const double* c = lv.coef + (int64_t)e * kCoef;
-        switch (lv.kinds[e]) {
-            case kDrift: el_drift(p, c); break;
-            case kQuad: el_quad(p, c); break;
-            case kSbend: el_sbend(p, c); break;
-            default: el_lens(p, c); break;
-        }
-    }
+    for (int32_t e = 0; e < lv.n; ++e) el_unified(p, lv.gen + (int64_t)e * kGen);
 }
 
 __device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {

@@ -28,6 +28,21 @@ struct ElemCoef {
     double c[kCoef];
 };
 
+// The same element as one unified sparse map (the union of the four kinds):
+//   x'  = fma(g2,  pt, fma(g1,  px, g0 * x))
+//   px' = fma(g5,  pt, fma(g4,  px, g3 * x))
+//   y'  = fma(g7,  py, g6 * y)
+//   py' = fma(g9,  py, g8 * y)
+//   t'  = fma(g12, pt, fma(g11, px, fma(g10, x, t)))
+// with unit and zero coefficients placed so that every kind gives exactly
+// the same result as its specialised map (a multiply by 1, an fma with a 0
+// factor and an fma adding +-0 are exact).  16 doubles, 3 unused.
+constexpr int kGen = 16;
+struct GenCoef {
+    double g[kGen];
+};
+GenCoef unify(int32_t kind, const ElemCoef& c);
+
 // ----------------------------------------------------------- stage params
 struct StageParams {
     double bg_in;          // (beta gamma)_ref at entry
@@ -47,8 +62,8 @@ struct StageParams {
 hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
                                 const double* mean, const double* sigma, int64_t i0,
                                 hipStream_t s);
-hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const int32_t* kinds,
-                                const double* coef, int32_t n_elem, hipStream_t s);
+hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, int32_t n_elem,
+                                hipStream_t s);
 hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind,
                                   const ElemCoef& c, hipStream_t s);
 struct LatticeView;

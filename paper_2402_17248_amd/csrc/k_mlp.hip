@@ -89,84 +89,62 @@ constexpr int kOffW0 = 0, kOffB0 = 384, kOffW1 = 448, kOffB1 = 4544, kOffW2 = 46
               kOffB2 = 8704, kOffW3 = 8768, kOffB3 = 9152;
 constexpr int kNParams = 9158;
 
-__global__ void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ img) {
-    const int l = threadIdx.x;  // one wavefront
+// Word w of lane l of the operand image (layout in the file comment).
+__device__ __forceinline__ uint32_t image_word(const float* __restrict__ p, int w, int l) {
     const int r = l % 16, g = l / 16;
     auto bfw = [](float v) { return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)v); };
-    // forward operands of the hidden layers 0..2 are built from c W and c b
-    const float c = kTanhScale;
-    // layer 0: slots 0-5 W_hi, 6-11 W_hi, 12-17 W_lo, rest 0
-    for (int mt = 0; mt < 4; ++mt) {
-        const int m = 16 * mt + r;
-        uint32_t w[4] = {0, 0, 0, 0};
-        for (int j = 0; j < 8; ++j) {
-            const int s = 8 * g + j;
+    const float c = kTanhScale;   // forward operands of hidden layers 0..2: c W, c b
+    uint32_t out = 0;
+    if (w < 16) {                                    // layer 0: slots 0-5 W_hi, 6-11 W_hi, 12-17 W_lo
+        const int m = 16 * (w / 4) + r, q = w % 4;
+        for (int h = 0; h < 2; ++h) {
+            const int s = 8 * g + 2 * q + h;
             float v = 0.0f;
             if (s < 18) {
-                const int f = s % 6;
-                const float wf = c * p[kOffW0 + m * kIn + f];
+                const float wf = c * p[kOffW0 + m * kIn + s % 6];
                 const float hi = bf16_round(wf);
                 v = (s < 12) ? hi : bf16_round(wf - hi);
             }
-            w[j / 2] |= bfw(v) << (16 * (j & 1));
+            out |= bfw(v) << (16 * h);
         }
-        for (int q = 0; q < 4; ++q) img[(4 * mt + q) * 64 + l] = w[q];
-    }
-    // layers 1, 2
-    for (int layer = 1; layer <= 2; ++layer) {
-        const float* W = p + (layer == 1 ? kOffW1 : kOffW2);
-        const int base = layer == 1 ? 16 : 48;
-        for (int mt = 0; mt < 4; ++mt)
-            for (int kc = 0; kc < 2; ++kc) {
-                const int m = 16 * mt + r;
-                uint32_t w[4] = {0, 0, 0, 0};
-                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(c * W[m * kW + perm_feature(kc, g, j)]) << (16 * (j & 1));
-                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * kc + q) * 64 + l] = w[q];
-            }
-    }
-    // layer 3 (output, unscaled): 6 output rows, rows 6..15 zero
-    for (int kc = 0; kc < 2; ++kc) {
-        uint32_t w[4] = {0, 0, 0, 0};
-        for (int j = 0; j < 8; ++j) {
-            const float v = r < kIn ? p[kOffW3 + r * kW + perm_feature(kc, g, j)] : 0.0f;
-            w[j / 2] |= bfw(v) << (16 * (j & 1));
+    } else if (w < 80) {                             // layers 1, 2 (forward)
+        const float* W = p + (w < 48 ? kOffW1 : kOffW2);
+        const int off = w - (w < 48 ? 16 : 48);
+        const int m = 16 * (off / 8) + r, kc = (off % 8) / 4, q = off % 4;
+        for (int h = 0; h < 2; ++h) out |= bfw(c * W[m * kW + perm_feature(kc, g, 2 * q + h)]) << (16 * h);
+    } else if (w < 88) {                             // layer 3 (output, unscaled), rows >= 6 zero
+        const int kc = (w - 80) / 4, q = (w - 80) % 4;
+        for (int h = 0; h < 2; ++h) {
+            const float v = r < kIn ? p[kOffW3 + r * kW + perm_feature(kc, g, 2 * q + h)] : 0.0f;
+            out |= bfw(v) << (16 * h);
         }
-        for (int q = 0; q < 4; ++q) img[(80 + 4 * kc + q) * 64 + l] = w[q];
-    }
-    // biases (FP32 bit patterns)
-    for (int layer = 0; layer < 3; ++layer) {
+    } else if (w < 136) {                            // hidden biases c b (FP32 bits)
+        const int layer = (w - 88) / 16, mt = ((w - 88) % 16) / 4, i = (w - 88) % 4;
         const float* b = p + (layer == 0 ? kOffB0 : layer == 1 ? kOffB1 : kOffB2);
-        for (int mt = 0; mt < 4; ++mt)
-            for (int i = 0; i < 4; ++i)
-                img[(88 + 16 * layer + 4 * mt + i) * 64 + l] = __float_as_uint(c * b[16 * mt + 4 * g + i]);
-    }
-    for (int i = 0; i < 4; ++i) {
-        const int row = 4 * g + i;
-        img[(136 + i) * 64 + l] = __float_as_uint(row < kIn ? p[kOffB3 + row] : 0.0f);
-    }
-    // transposed layer 3: A[m][8g + j] = W3[4g + j][m] for j < 4, 4g + j < 6
-    for (int mt = 0; mt < 4; ++mt) {
-        const int m = 16 * mt + r;
-        uint32_t w[4] = {0, 0, 0, 0};
-        for (int j = 0; j < 4; ++j) {
-            const int row = 4 * g + j;
-            const float v = row < kIn ? p[kOffW3 + row * kW + m] : 0.0f;
-            w[j / 2] |= bfw(v) << (16 * (j & 1));
+        out = __float_as_uint(c * b[16 * mt + 4 * g + i]);
+    } else if (w < 140) {                            // output bias
+        const int row = 4 * g + (w - 136);
+        out = __float_as_uint(row < kIn ? p[kOffB3 + row] : 0.0f);
+    } else if (w < 156) {                            // W3^T: A[m][8g + j] = W3[4g + j][m], j < 4
+        const int m = 16 * ((w - 140) / 4) + r, q = (w - 140) % 4;
+        for (int h = 0; h < 2; ++h) {
+            const int j = 2 * q + h, row = 4 * g + j;
+            const float v = (j < 4 && row < kIn) ? p[kOffW3 + row * kW + m] : 0.0f;
+            out |= bfw(v) << (16 * h);
         }
-        for (int q = 0; q < 4; ++q) img[(140 + 4 * mt + q) * 64 + l] = w[q];
+    } else {                                         // W2^T (156..187), W1^T (188..219)
+        const float* W = p + (w < 188 ? kOffW2 : kOffW1);
+        const int off = w - (w < 188 ? 156 : 188);
+        const int m = 16 * (off / 8) + r, kc = (off % 8) / 4, q = off % 4;
+        for (int h = 0; h < 2; ++h) out |= bfw(W[perm_feature(kc, g, 2 * q + h) * kW + m]) << (16 * h);
     }
-    // transposed layers 2, 1: A[m][slot] = W[perm_feature(c, g, j)][m]
-    for (int layer = 2; layer >= 1; --layer) {
-        const float* W = p + (layer == 1 ? kOffW1 : kOffW2);
-        const int base = layer == 2 ? 156 : 188;
-        for (int mt = 0; mt < 4; ++mt)
-            for (int kc = 0; kc < 2; ++kc) {
-                const int m = 16 * mt + r;
-                uint32_t w[4] = {0, 0, 0, 0};
-                for (int j = 0; j < 8; ++j) w[j / 2] |= bfw(W[perm_feature(kc, g, j) * kW + m]) << (16 * (j & 1));
-                for (int q = 0; q < 4; ++q) img[(base + 8 * mt + 4 * kc + q) * 64 + l] = w[q];
-            }
-    }
+    return out;
+}
+
+// One thread per image word: kImgWords words x 64 lanes.
+__global__ __launch_bounds__(256) void k_mlp_pack(const float* __restrict__ p, uint32_t* __restrict__ img) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < kImgWords * 64) img[t] = image_word(p, t / 64, t % 64);
 }
 
 struct NormArgs {
@@ -580,22 +558,40 @@ struct AdamArgs {
     float b1, b2, eps;
 };
 
-// Adam (Kingma & Ba 2015), bias-corrected, FP32 master weights.
+// Adam (Kingma & Ba 2015), bias-corrected, FP32 master weights.  Block:
+// 64 parameters; thread quarter q sums the block partials q, q+4, ... and
+// the four quarter sums are added in a fixed order.  Block 0 also adds the
+// loss partials (strided per thread, then a fixed tree).
+constexpr int kAdamPer = 64;
 __global__ __launch_bounds__(256) void k_train_adam(AdamArgs a) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < kNParams) {
-        float g = 0.0f;
-        for (int b = 0; b < a.nb; ++b) g += a.part[(int64_t)b * kNParams + i];
+    __shared__ float red[4][kAdamPer];
+    __shared__ double lred[256];
+    const int pl = threadIdx.x % kAdamPer, q = threadIdx.x / kAdamPer;
+    const int i = blockIdx.x * kAdamPer + pl;
+    float g = 0.0f;
+    if (i < kNParams)
+        for (int b = q; b < a.nb; b += 4) g += a.part[(int64_t)b * kNParams + i];
+    red[q][pl] = g;
+    if (blockIdx.x == 0) {
+        double sum = 0.0;
+        for (int b = threadIdx.x; b < a.nb; b += 256) sum += (double)a.loss_part[b];
+        lred[threadIdx.x] = sum;
+    }
+    __syncthreads();
+    if (q == 0 && i < kNParams) {
+        g = (red[0][pl] + red[1][pl]) + (red[2][pl] + red[3][pl]);
         const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
         const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
         a.m[i] = m;
         a.v[i] = v;
         a.p[i] = a.p[i] - a.lr_c1 * m / (sqrtf(v * a.inv_c2) + a.eps);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double sum = 0.0;
-        for (int b = 0; b < a.nb; ++b) sum += (double)a.loss_part[b];
-        *a.loss_acc += sum * a.loss_scale;
+    if (blockIdx.x == 0) {
+        for (int w = 128; w >= 1; w >>= 1) {
+            if ((int)threadIdx.x < w) lred[threadIdx.x] += lred[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *a.loss_acc += lred[0] * a.loss_scale;
     }
 }
 
@@ -677,7 +673,7 @@ int mlp_nparams() { return kNParams; }
 int mlp_image_words() { return kImgWords * 64; }
 
 hipError_t launch_mlp_pack(const float* params, uint32_t* img, hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(64), 0, s, params, img);
+    hipLaunchKernelGGL(k_mlp_pack, dim3((kImgWords * 64 + 255) / 256), dim3(256), 0, s, params, img);
     return hipGetLastError();
 }
 
@@ -728,7 +724,7 @@ hipError_t launch_train_adam(float* p, float* m, float* v, const float* part, in
     a.b1 = b1;
     a.b2 = b2;
     a.eps = eps;
-    hipLaunchKernelGGL(k_train_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_train_adam, dim3((kNParams + kAdamPer - 1) / kAdamPer), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

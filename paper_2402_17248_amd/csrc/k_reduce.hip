@@ -214,22 +214,25 @@ __global__ __launch_bounds__(kBlock) void k_merge(const DD* __restrict__ part, i
 
 __global__ void k_moments_final(const DD* __restrict__ tot, const double* __restrict__ z, int64_t ld,
                                 int64_t n, double* __restrict__ out) {
-    if (threadIdx.x == 0) {
-        const double nd = (double)n;
-        for (int j = 0; j < 6; ++j) {
-            // mean = shift + S/n, the shift being particle 0
-            const DD m = dd_div_d(tot[j], nd);
-            const DD mean = dd_add(DD{z[(int64_t)j * ld], 0.0}, m);
-            out[j] = mean.hi + mean.lo;
+    // one thread per output: 6 means, then the 21 upper-triangle covariances
+    const int q = threadIdx.x;
+    const double nd = (double)n;
+    if (q < 6) {
+        // mean = shift + S/n, the shift being particle 0
+        const DD m = dd_div_d(tot[q], nd);
+        const DD mean = dd_add(DD{z[(int64_t)q * ld], 0.0}, m);
+        out[q] = mean.hi + mean.lo;
+    } else if (q < 27) {
+        int j = 0, r = q - 6;
+        while (r >= 6 - j) {
+            r -= 6 - j;
+            ++j;
         }
-        int q = 6;
-        for (int j = 0; j < 6; ++j)
-            for (int k = j; k < 6; ++k, ++q) {
-                DD t = dd_div_d(dd_mul(tot[j], tot[k]), nd);
-                DD u = dd_add(tot[q], dd_neg(t));
-                DD c = dd_div_d(u, nd);
-                out[q] = c.hi + c.lo;
-            }
+        const int k = j + r;
+        const DD t = dd_div_d(dd_mul(tot[j], tot[k]), nd);
+        const DD u = dd_add(tot[q], dd_neg(t));
+        const DD c = dd_div_d(u, nd);
+        out[q] = c.hi + c.lo;
     }
 }
 

@@ -2,8 +2,8 @@
 as a transfer map; the traditional map is linear).  A surrogate trained on the
 GPU by the library's own kernels is compared, on a fresh bunch, with the
 affine least-squares transfer map fitted to the same training pairs, both
-against the fine-step stage.  The bounds are loose on purpose (short
-training); the benchmark reports the full-length numbers."""
+against the fine-step stage.  The bounds are loose on purpose (a quarter of the
+benchmark's pairs); the benchmark reports the full-length numbers."""
 import numpy as np
 import pytest
 
@@ -32,7 +32,7 @@ def test_network_beats_linear_transfer_map():
     entry = ref.copy()
     hbl.apply_stage(zout, wl.beamline[1], ref, record=zin, n=n_pairs)
     sur = hbl.Surrogate(W.mlp_init_seed(1))
-    log = sur.train(zin, zout, n_pairs, batch=4096, epochs=60, lr=1e-3, lr_final=1e-5,
+    log = sur.train(zin, zout, n_pairs, batch=4096, epochs=300, lr=1e-3, lr_final=1e-5,
                     shuffle_seed=W.shuffle_seed(1))
     assert log[-1, 1] < 0.05 * log[0, 1]          # test loss fell by > 20x
 
@@ -56,6 +56,6 @@ def test_network_beats_linear_transfer_map():
     zl[:, :n] = lin
     rms_lin, _, eps_lin = hbl.compare(zl, f, n=n)
 
-    assert max(abs(eps_nn[0]), abs(eps_nn[1])) < 1e-2
-    assert min(abs(eps_lin[0]), abs(eps_lin[1])) > 0.5      # the linear map misses the filamentation
-    assert max(rms_nn[:2]) < 0.1 * min(rms_lin[:2])
+    assert max(abs(eps_nn[0]), abs(eps_nn[1])) < 2e-2, eps_nn
+    assert min(abs(eps_lin[0]), abs(eps_lin[1])) > 0.5, eps_lin   # the linear map misses the filamentation
+    assert max(rms_nn[:2]) < 0.1 * min(rms_lin[:2]), (rms_nn, rms_lin)
