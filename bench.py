@@ -35,9 +35,10 @@ VALU_PEAK_TSLOTS = 256 * 4 * 32 * 2.4e9 / 1e12                      # 78.6 T slo
 # tanh(a) = 1 - 2/(2^(c a) + 1): exp2 (4) + add (1) + reciprocal (4) + fma (1) = 10 slots,
 # 3 hidden layers x 64 activations per particle
 ALU_SLOTS_PER_PARTICLE = 3 * 64 * 10                                 # 1,920
-# HBM bytes per launch of the dominant kernel read from the FETCH_SIZE / WRITE_SIZE
-# counter runs (scaled by a plain copy); None until taken for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counter
+# runs of `--pmc-probe` (FETCH scaled x2.0, WRITE x1.0 by a 1 GiB device copy), averaged
+# over its eight launches on 2.5e7 particles; to be re-taken whenever the kernel changes.
+TRAFFIC_BYTES_PER_LAUNCH = 2.4004e9
 
 
 def parse():
@@ -358,7 +359,8 @@ def main():
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
         "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,
                      "unit": "T VALU slots/s", "frac": alu_achieved / VALU_PEAK_TSLOTS,
-                     "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                     "traffic": TRAFFIC_BYTES_PER_LAUNCH if n == 25_000_000 else None,
+                     "traffic_unit": "HBM bytes per launch (algorithmic 96 B/particle)",
                      "kernel": "k_mlp_infer<gaps> (surrogate inference, transport gaps fused)"},
         "cpu_baseline": cpu,
     }
