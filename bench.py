@@ -47,12 +47,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=25_000_000)
-    ap.add_argument("--epochs", type=int, default=300, help="training epochs per surrogate")
+    ap.add_argument("--epochs", type=int, default=1200, help="training epochs per surrogate")
     ap.add_argument("--pairs", type=int, default=1 << 20)
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-single-stage", action="store_true", help="skip the single-stage (C4) study")
+    ap.add_argument("--no-single-stage", action="store_true",
+                    help="skip the equal-error chain comparison and the single-stage (C4) study")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter passes: one plain device copy of 1 GiB "
                          "(calibration), then the benchmark's four surrogate passes (inference "
@@ -236,6 +237,63 @@ def single_stage_study(args, log):
     return out, t_inf
 
 
+def chain_equal_error(args, wl, chain, dt_sur, step_fn, log):
+    """The staged chain at equal error: on the first 1e6 particles of the
+    benchmark bunch, the emittance error of the surrogate chain and of the
+    fine-step chain at a given substep count are measured against the
+    fine-step chain at 32,000 substeps per stage; the substep count whose
+    error equals the surrogate chain's is found by bisection and that
+    fine-step chain is timed on the full bunch like the benchmark step."""
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+    from paper_2402_17248_amd.chain import Chain
+
+    m = 1_000_000
+    sig = wl.bunch.sigma
+    z0 = hbl.new_bunch(m)
+    hbl.fill_gaussian(z0, wl.bunch.seed, (0.0,) * 6, sig, n=m)
+
+    def fine(nsub, n, z):
+        c = Chain(W.c5_chain(n=n, nsub=nsub).beamline, wl.E_MeV)
+        c.run(z, n=n)
+        return c
+
+    conv = z0.clone()
+    fine(32000, m, conv)
+    zs = z0.clone()
+    chain.run(zs, n=m, use_surrogates=True)
+    err_s = max(abs(e) for e in hbl.compare(zs, conv, n=m)[2][:2])
+
+    def err_fine(nsub):
+        zf = z0.clone()
+        fine(nsub, m, zf)
+        return max(abs(e) for e in hbl.compare(zf, conv, n=m)[2][:2])
+
+    err_2000 = err_fine(wl.beamline[1].nsub)
+    lo, hi = 50, 32000
+    if err_fine(lo) <= err_s:
+        hi = lo
+    while hi - lo > max(1, lo // 50):
+        mid = (lo + hi) // 2
+        if err_fine(mid) <= err_s:
+            hi = mid
+        else:
+            lo = mid
+    n_eq = hi
+    del z0, conv, zs
+    eq_chain = Chain(W.c5_chain(n=wl.bunch.n, nsub=n_eq).beamline, wl.E_MeV)
+    dt_eq = step_fn(eq_chain, 2, 1)
+    n = wl.bunch.n
+    log(f"chain at equal error: surrogate emittance error {err_s:.3e} vs 32000-substep chain "
+        f"(2000 substeps: {err_2000:.3e}); fine-step chain needs {n_eq} substeps per stage: "
+        f"{dt_eq * 1e3:.3f} ms/step, surrogate chain {dt_eq / dt_sur:.1f}x faster")
+    return {"eps_err_vs_32000_substep_chain": {"surrogate": err_s, "fine_step_2000": err_2000},
+            "fine_step_equal_error_nsub": n_eq, "fine_step_equal_error_ms_per_step": dt_eq * 1e3,
+            "fine_step_equal_error_particles_per_s": n / dt_eq, "speedup_at_equal_error": dt_eq / dt_sur}
+
+
 def main():
     args = parse()
     if args.pmc_probe:
@@ -303,6 +361,20 @@ def main():
         per_launch = sum(a.elapsed_time(b) for a, b in evs) * 1e-3 / steps / n_pass
         return dt, per_launch
 
+    def time_chain(c, steps, warmup):
+        def one():
+            hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
+            c.run(z, n=n)
+            hbl.moments_async(z, out27, n=n)
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
     dt_sur, t_inf = timed(True, args.steps, args.warmup)
     log(f"surrogate chain: {dt_sur * 1e3:.3f} ms/step, {n / dt_sur:.4g} particles/s")
     dt_fine, t_fs = timed(False, args.fine_steps, 1)
@@ -317,6 +389,10 @@ def main():
     rms, cen, eps_rel = hbl.compare(zs, z, n=n)
     log(f"surrogate vs fine-step chain: eps_rel x,y,t = {eps_rel}, rms/sigma = {rms}")
     del zs
+
+    equal = None
+    if not args.no_single_stage:
+        equal = chain_equal_error(args, wl, chain, dt_sur, time_chain, log)
 
     single = None
     if not args.no_single_stage:
@@ -355,6 +431,7 @@ def main():
                                "speedup": t_fs / t_inf, "launches_per_step": n_pass,
                                "dense_mfma_tflops": mfma_achieved,
                                "dense_mfma_frac": mfma_achieved / BF16_PEAK_TFLOPS},
+        "chain_equal_error": equal,
         "single_stage_c4": single,
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
         "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,
