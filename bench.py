@@ -98,12 +98,23 @@ def log(msg):
 
 def time_events(torch, fn, iters, setup=None):
     """Average duration of fn() by HIP events on torch's current stream, the
-    stream every library call below is enqueued on; setup() (untimed) runs
-    before each timed call."""
+    stream every library call below is enqueued on.  Without setup the calls
+    run back to back inside one pair of events; with setup, setup() (untimed,
+    enqueued first, so the device is busy while the host enqueues the call)
+    runs before each separately bracketed call."""
+    if setup is None:
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        fn()
+        s.record()
+        for _ in range(iters):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / iters * 1e-3
     total = 0.0
     for _ in range(iters):
-        if setup is not None:
-            setup()
+        setup()
         s = torch.cuda.Event(enable_timing=True)
         e = torch.cuda.Event(enable_timing=True)
         s.record()
@@ -117,20 +128,25 @@ def time_events(torch, fn, iters, setup=None):
 def cpu_baseline(wl, chain, budget_s):
     """The oracle, as it stands, on a bounded sample of the same workload:
     the staged beamline with the trained surrogates evaluated by the oracle's
-    FP64 network, serial, one core."""
+    FP64 network.  Serial on one core, then the same per-particle code on a
+    thread pool over contiguous particle ranges (the oracle keeps no global
+    state; ctypes releases the interpreter lock during its calls)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle
-    from paper_2402_17248_amd import hbl
 
     params = [s.get_params() for s in chain.surrogates]
     norms = [np.array(s.get_norm()) for s in chain.surrogates]
     sh = oracle.shape()
+    oracle.lib()
 
-    def run(m):
-        z = oracle.fill_gaussian(m, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma)
+    def fill(m, i0=0):
+        return oracle.fill_gaussian(m, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, i0=i0)
+
+    def track(z):
         ref = oracle.Ref.from_energy(wl.E_MeV)
-        t0 = time.perf_counter()
         k = 0
         for seg in wl.beamline:
             if isinstance(seg, list):
@@ -139,14 +155,29 @@ def cpu_baseline(wl, chain, budget_s):
                 z = oracle.mlp_apply(sh, params[k], norms[k], z, mode=0)
                 ref.gamma += seg.dE_MeV / ref.mass_MeV
                 k += 1
+        return z
+
+    def timed_track(z):
+        t0 = time.perf_counter()
+        track(z)
         return time.perf_counter() - t0
 
-    t_small = run(256) / 256
-    m = int(max(256, min(wl.bunch.n, budget_s / max(t_small, 1e-12))))
-    t = run(m)
-    return {"value": m / t, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} particles of the {wl.bunch.n}-particle bunch through the full staged "
-                      f"beamline (lattice gaps + 4 surrogate stages), serial FP64 oracle, {t:.1f} s"}
+    t_small = timed_track(fill(256)) / 256
+    m1 = int(max(256, min(wl.bunch.n, 0.5 * budget_s / max(t_small, 1e-12))))
+    t1 = timed_track(fill(m1))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    m2 = min(wl.bunch.n, m1 * threads)
+    per = (m2 + threads - 1) // threads
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        chunks = list(ex.map(lambda i: fill(min(per, m2 - i), i), range(0, m2, per)))
+        t0 = time.perf_counter()
+        list(ex.map(track, chunks))
+        t2 = time.perf_counter() - t0
+    return {"value": m2 / t2, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m2} particles of the {wl.bunch.n}-particle bunch through the full staged "
+                      f"beamline (lattice gaps + 4 surrogate stages, FP64 network), {threads} threads over "
+                      f"particle ranges, {t2:.1f} s wall (fill excluded)",
+            "serial_value": m1 / t1, "serial_sample": f"first {m1} particles on one core, {t1:.1f} s"}
 
 
 def single_stage_study(args, log):
@@ -235,6 +266,71 @@ def single_stage_study(args, log):
         f"{t_fine*1e3:.3f} ms ({t_fine/t_inf:.1f}x); equal-error fine-step nsub {n_eq} "
         f"({t_fine_eq*1e3:.3f} ms, {t_fine_eq/t_inf:.1f}x)")
     return out, t_inf
+
+
+def config_studies(log):
+    """Timing of the other benchmark configurations, each in the launch shape
+    its parity tests use: C1 (FODO, 1e4), C2 (58-element fused lattice on
+    1e6, warm and with the 256 MB last-level cache flushed, the unfused
+    comparator, and 1e7 / 2.5e7 for the HBM fraction), C3 (2000-substep stage
+    on 1e6)."""
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+
+    out = {}
+    wl = W.c1_fodo()
+    n = wl.bunch.n
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    lat = hbl.Lattice(wl.beamline[0], ref)
+    t = time_events(torch, lambda: lat.push(z, ref.copy(), n=n), 50)
+    out["c1_fodo_1e4"] = {"fused_us": t * 1e6, "particles_per_s": n / t,
+                          "element_pushes_per_s": lat.n_elem * n / t}
+
+    wl = W.c2_fused()
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    lat = hbl.Lattice(wl.beamline[0], ref)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB > 256 MB cache
+    c2 = {"elements": lat.n_elem}
+    for n, key in ((1_000_000, "n_1e6"), (10_000_000, "n_1e7"), (25_000_000, "n_2.5e7")):
+        z = hbl.new_bunch(n)
+        hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+        t = time_events(torch, lambda: lat.push(z, ref.copy(), n=n), 10)
+        row = {"fused_us": t * 1e6, "hbm_frac": 96.0 * n / t / (HBM_PEAK_GBS * 1e9),
+               "element_pushes_per_s": lat.n_elem * n / t}
+        if n == 1_000_000:
+            tc = time_events(torch, lambda: lat.push(z, ref.copy(), n=n), 10, setup=lambda: flush.fill_(1.0))
+            tu = time_events(torch, lambda: lat.push(z, ref.copy(), n=n, fused=False), 5)
+            row.update({"fused_cold_us": tc * 1e6, "hbm_frac_cold": 96.0 * n / tc / (HBM_PEAK_GBS * 1e9),
+                        "unfused_us": tu * 1e6, "fused_speedup": tu / t})
+        c2[key] = row
+        del z
+    del flush
+    out["c2_lattice58"] = c2
+
+    wl = W.c3_stage()
+    n = wl.bunch.n
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
+    st = wl.beamline[1]
+    t = time_events(torch, lambda: hbl.apply_stage(z, st, ref.copy(), n=n), 3)
+    sub = st.nsub * n
+    out["c3_stage_1e6"] = {"stage_ms": t * 1e3, "particles_per_s": n / t,
+                           "substep_pushes_per_s": sub / t,
+                           "fp64_tflops_algorithmic": 10.0 * sub / t / 1e12,
+                           "fp64_flop_frac": 10.0 * sub / t / 1e12 / FP64_PEAK_TFLOPS,
+                           "fp64_issue_frac": 11.0 * sub / t / (FP64_PEAK_TFLOPS / 2 * 1e12)}
+    log(f"configs: C1 {out['c1_fodo_1e4']['fused_us']:.1f} us; C2 1e6 fused "
+        f"{c2['n_1e6']['fused_us']:.1f} us warm / {c2['n_1e6']['fused_cold_us']:.1f} us cold, unfused "
+        f"{c2['n_1e6']['unfused_us']:.1f} us, 2.5e7 {c2['n_2.5e7']['fused_us']:.0f} us "
+        f"({c2['n_2.5e7']['hbm_frac']:.0%} of HBM); C3 stage {out['c3_stage_1e6']['stage_ms']:.3f} ms "
+        f"({out['c3_stage_1e6']['fp64_issue_frac']:.0%} of FP64 issue)")
+    return out
 
 
 def chain_equal_error(args, wl, chain, dt_sur, step_fn, log):
@@ -390,9 +486,10 @@ def main():
     log(f"surrogate vs fine-step chain: eps_rel x,y,t = {eps_rel}, rms/sigma = {rms}")
     del zs
 
-    equal = None
+    equal = configs = None
     if not args.no_single_stage:
         equal = chain_equal_error(args, wl, chain, dt_sur, time_chain, log)
+        configs = config_studies(log)
 
     single = None
     if not args.no_single_stage:
@@ -432,6 +529,7 @@ def main():
                                "dense_mfma_tflops": mfma_achieved,
                                "dense_mfma_frac": mfma_achieved / BF16_PEAK_TFLOPS},
         "chain_equal_error": equal,
+        "other_configs": configs,
         "single_stage_c4": single,
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
         "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,

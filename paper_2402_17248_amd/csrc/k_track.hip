@@ -122,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
             if (live[k]) load6(z, ld, i, p[k]);
             else p[k] = P6{0, 0, 0, 0, 0, 0};
         }
+#pragma unroll 2
         for (int32_t e = 0; e < n_elem; ++e) {
             const double* g = gen + (int64_t)e * kGen;
 #pragma unroll
