@@ -158,3 +158,30 @@ def test_stage_edge_cases(hbl, orc, nsub, dE):
     oref = orc.Ref.from_energy(1000.0)
     orc.push(c, [st], oref)
     assert rel_err(to_host(z, n), c).max() < TOL
+
+
+def test_stage_time_reversal_full_size(hbl):
+    """A property that holds for every particle at any size: the stage run
+    forward, then backward (transverse momenta reversed, decelerating ramp,
+    same substeps), returns the C3 bunch (1e6 particles, 2000 substeps) to
+    its start; pt exactly up to rounding."""
+    torch = __import__("torch")
+    wl = W.c3_stage()
+    n = wl.bunch.n
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+    z0 = z.clone()
+    st = wl.beamline[1]
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    hbl.apply_stage(z, st, ref, n=n)
+    z[3:5, :n] *= -1
+    back = W.Stage(L=st.L, n0_m3=st.n0_m3, dE_MeV=-st.dE_MeV, nsub=st.nsub)
+    hbl.apply_stage(z, back, ref, n=n)
+    z[3:5, :n] *= -1
+    torch.cuda.synchronize()
+    assert abs(ref.gamma / hbl.Ref.from_energy(wl.E_MeV).gamma - 1) < 1e-15
+    d = (z[:, :n] - z0[:, :n]).abs().amax(dim=1).cpu().numpy()
+    # angles inside the channel reach ~1e-2 (x / beta); positions ~1e-5
+    assert d[X] < 1e-12 * 10e-6 and d[1] < 1e-12 * 10e-6, d
+    assert d[PX] < 1e-12 * 1e-2 and d[4] < 1e-12 * 1e-2, d
+    assert d[PT] < 1e-15 * 1e-3 * 10, d

@@ -5,7 +5,7 @@ gamma_i ramping linearly.  Pinned against closed forms that do not share the
 integrator's steps: the Chebyshev power of a unimodular 2x2 matrix (no ramp),
 the continuous cos/sin solution, the Bessel solution of the ramped equation,
 the matched-beam scaling laws of the paper (§4), the determinant of the
-transverse Jacobian, and the flight-time integral.
+transverse Jacobian, the flight-time integral, and time reversal.
 """
 import math
 import os
@@ -229,3 +229,39 @@ def test_chromatic_stage_grows_emittance(orc):
     _, c1 = orc.moments(z)
     en1 = orc.emittances(c1)[0] * math.sqrt(ref.gamma**2 - 1)
     assert en1 > 10 * en0
+
+
+@pytest.mark.parametrize("nsub", [200, 2000])
+def test_time_reversal(orc, nsub):
+    """The kick-drift-kick step with the ramp evaluated at each substep's
+    midpoint is time-symmetric: reversing the transverse momenta and running
+    the decelerating stage (gamma_out -> gamma_in over the same length and
+    substeps) returns every particle to its start, for any step count.  A
+    ramp sampled at the substep ends, or an asymmetric split of the kicks,
+    breaks this.  pt returns exactly (both stages rescale by a ratio of
+    beta*gamma); t picks up the two first-order flight-time terms."""
+    E, dE = 1000.0, 9000.0
+    z = probe_particles(n=16, seed=5)
+    z[PT] *= 10.0                      # strongly chromatic: phase depends on pt
+    z0 = z.copy()
+    ref = run_stage(orc, z, E, dE, nsub)
+    t_fwd = z[T] - z0[T]
+    z[PX] *= -1
+    z[PY] *= -1
+    run_stage(orc, z, E + dE, -dE, nsub)
+    z[PX] *= -1
+    z[PY] *= -1
+    # inside the channel the angles reach ~x/beta ~ 1e-2, a hundred times the entrance
+    # spread, so px, py return to ~1e-14 of their internal scale
+    for j, s in ((X, 10e-6), (Y, 10e-6), (PX, 1e-2), (PY, 1e-2)):
+        assert np.abs(z[j] - z0[j]).max() < 1e-13 * s, j
+    # one substep more on the way back (a different midpoint grid) does not return
+    w = z0.copy()
+    run_stage(orc, w, E, dE, nsub)
+    w[PX] *= -1
+    w[PY] *= -1
+    run_stage(orc, w, E + dE, -dE, nsub + 1)
+    assert np.abs(w[X] - z0[X]).max() > 1e3 * 1e-13 * 10e-6
+    assert np.allclose(z[PT], z0[PT], rtol=4e-16, atol=0)
+    # t: each pass adds R56 * pt_at_entry, and R56_back * pt_out = R56 * pt_in here
+    assert np.allclose(z[T] - z0[T], 2 * t_fwd, rtol=1e-12, atol=1e-30)
