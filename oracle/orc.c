@@ -121,7 +121,34 @@ static void apply_drift(double* z, int64_t n, int64_t ld, double L, double bg)
     }
 }
 
-static void apply_quad(double* z, int64_t n, int64_t ld, double L, double k, double bg)
+/* Chromatic focusing: a particle with relative momentum deviation delta
+ * (to first order delta = -pt / beta) sees the strength k / (1 + delta)
+ * ~ k (1 - delta).  With w = sqrt|k| the plane matrix [[a, b], [c, a]] then
+ * changes, to first order in delta, by delta * [[a', b'], [c', a']], the
+ * derivative of the matrix along dw/ddelta = -w/2:
+ *   focusing (cos):     a' = (wL/2) sin wL,  b' = (sin wL / w - L cos wL)/2,
+ *                       c' = (w/2)(sin wL + wL cos wL)
+ *   defocusing (cosh):  a' = -(wL/2) sinh wL, b' = (sinh wL / w - L cosh wL)/2,
+ *                       c' = -(w/2)(sinh wL + wL cosh wL)
+ * (the w -> 0 limits vanish).  Drifts and the px = dx/ds relation stay
+ * those of the reference momentum, as in the achromatic maps. */
+static void chrom_plane(int focusing, double w, double L, double* da, double* db, double* dc)
+{
+    if (w == 0.0) { *da = *db = *dc = 0.0; return; }
+    double wl = w * L;
+    if (focusing) {
+        *da = 0.5 * wl * sin(wl);
+        *db = 0.5 * (sin(wl) / w - L * cos(wl));
+        *dc = 0.5 * w * (sin(wl) + wl * cos(wl));
+    } else {
+        *da = -0.5 * wl * sinh(wl);
+        *db = 0.5 * (sinh(wl) / w - L * cosh(wl));
+        *dc = -0.5 * w * (sinh(wl) + wl * cosh(wl));
+    }
+}
+
+static void apply_quad(double* z, int64_t n, int64_t ld, double L, double k, double bg, double beta,
+                       int chromatic)
 {
     if (k == 0.0) { apply_drift(z, n, ld, L, bg); return; }
     double w = sqrt(fabs(k));
@@ -131,15 +158,22 @@ static void apply_quad(double* z, int64_t n, int64_t ld, double L, double k, dou
     double ax, bx, cx, ay, by, cy;   /* [[a, b], [c, a]] per plane */
     if (k > 0) { ax = fc; bx = fs; cx = fm; ay = dc; by = ds; cy = dm; }
     else       { ax = dc; bx = ds; cx = dm; ay = fc; by = fs; cy = fm; }
+    /* chromatic derivatives per plane, zero when achromatic */
+    double dax = 0, dbx = 0, dcx = 0, day = 0, dby = 0, dcy = 0;
+    if (chromatic) {
+        chrom_plane(k > 0, w, L, &dax, &dbx, &dcx);
+        chrom_plane(k < 0, w, L, &day, &dby, &dcy);
+    }
     double r56 = L / (bg * bg);
     double* x = ROW(z, 0, ld); double* y = ROW(z, 1, ld); double* t = ROW(z, 2, ld);
     double* px = ROW(z, 3, ld); double* py = ROW(z, 4, ld); double* pt = ROW(z, 5, ld);
     for (int64_t i = 0; i < n; i++) {
         double x0 = x[i], px0 = px[i], y0 = y[i], py0 = py[i];
-        x[i] = ax * x0 + bx * px0;
-        px[i] = cx * x0 + ax * px0;
-        y[i] = ay * y0 + by * py0;
-        py[i] = cy * y0 + ay * py0;
+        double d = -pt[i] / beta;
+        x[i] = ax * x0 + bx * px0 + d * (dax * x0 + dbx * px0);
+        px[i] = cx * x0 + ax * px0 + d * (dcx * x0 + dax * px0);
+        y[i] = ay * y0 + by * py0 + d * (day * y0 + dby * py0);
+        py[i] = cy * y0 + ay * py0 + d * (dcy * y0 + day * py0);
         t[i] = t[i] + r56 * pt[i];
     }
 }
@@ -180,13 +214,15 @@ static void apply_sbend(double* z, int64_t n, int64_t ld, double L, double th, d
     }
 }
 
-static void apply_lens(double* z, int64_t n, int64_t ld, double f)
+/* Thin lens; chromatic: focal length f (1 + delta), first order in delta. */
+static void apply_lens(double* z, int64_t n, int64_t ld, double f, double beta, int chromatic)
 {
     double* x = ROW(z, 0, ld); double* y = ROW(z, 1, ld);
-    double* px = ROW(z, 3, ld); double* py = ROW(z, 4, ld);
+    double* px = ROW(z, 3, ld); double* py = ROW(z, 4, ld); double* pt = ROW(z, 5, ld);
     for (int64_t i = 0; i < n; i++) {
-        px[i] = px[i] - x[i] / f;
-        py[i] = py[i] - y[i] / f;
+        double s = chromatic ? 1.0 + pt[i] / beta : 1.0;     /* 1 - delta */
+        px[i] = px[i] - x[i] * s / f;
+        py[i] = py[i] - y[i] * s / f;
     }
 }
 
@@ -214,15 +250,22 @@ static int apply_stage(double* z, int64_t n, int64_t ld, const orc_elem* st, orc
                                    : bg_in * (1.0 / (g_in * g_in) - 1.0 / (g_out * g_out)) / (2.0 * gp);
     double* x = ROW(z, 0, ld); double* y = ROW(z, 1, ld); double* t = ROW(z, 2, ld);
     double* px = ROW(z, 3, ld); double* py = ROW(z, 4, ld); double* pt = ROW(z, 5, ld);
+    /* Energy-correlated gain: particle i gains dE (1 + chirp t_i), t_i its
+     * entry t, so its own gradient is gp (1 + chirp t_i).  Its flight time
+     * then carries -chirp t_i gp * integral s / gamma_ref(s)^3 ds
+     * = -chirp t_i gp L^2 / (2 gamma_in gamma_out^2). */
+    const double chirp = st->chirp;
+    const double t_chirp = gp * L * L / (2.0 * g_in * g_out * g_out);
     for (int64_t i = 0; i < n; i++) {
-        double pt_in = pt[i];
+        double pt_in = pt[i], t_in = t[i];
         double dg = -pt_in * bg_in;
+        double gpi = gp * (1.0 + chirp * t_in);
         double xi = x[i], yi = y[i];
         double ux = px[i] * bg_in, uy = py[i] * bg_in;
         for (int64_t s = 0; s < N; s++) {
             ux = ux - 0.5 * h * kappa * xi;
             uy = uy - 0.5 * h * kappa * yi;
-            double gam = g_in + gp * (((double)s + 0.5) * h) + dg;
+            double gam = g_in + gpi * (((double)s + 0.5) * h) + dg;
             xi = xi + h * ux / gam;
             yi = yi + h * uy / gam;
             ux = ux - 0.5 * h * kappa * xi;
@@ -230,8 +273,9 @@ static int apply_stage(double* z, int64_t n, int64_t ld, const orc_elem* st, orc
         }
         x[i] = xi; y[i] = yi;
         px[i] = ux / bg_out; py[i] = uy / bg_out;
-        t[i] = t[i] + r56 * pt_in;
-        pt[i] = pt_in * bg_in / bg_out;
+        t[i] = t_in + r56 * pt_in - chirp * t_in * t_chirp;
+        /* E_i,out - E_ref,out = -pt_in bg_in + chirp t_in (g_out - g_in)  (units m c^2) */
+        pt[i] = (pt_in * bg_in - chirp * t_in * (g_out - g_in)) / bg_out;
     }
     ref->gamma = g_out;
     ref->s += L;
@@ -246,11 +290,11 @@ int orc_push(double* z, int64_t n, int64_t ld, const orc_elem* e, int32_t n_elem
         ref_kin(ref, &bg, &beta);
         switch (e[j].kind) {
         case ORC_DRIFT: apply_drift(z, n, ld, e[j].L, bg); ref->s += e[j].L; break;
-        case ORC_QUAD: apply_quad(z, n, ld, e[j].L, e[j].k, bg); ref->s += e[j].L; break;
+        case ORC_QUAD: apply_quad(z, n, ld, e[j].L, e[j].k, bg, beta, e[j].chromatic); ref->s += e[j].L; break;
         case ORC_SBEND: apply_sbend(z, n, ld, e[j].L, e[j].angle, bg, beta); ref->s += e[j].L; break;
         case ORC_THIN_LENS:
             if (e[j].f == 0.0) return -1;
-            apply_lens(z, n, ld, e[j].f);
+            apply_lens(z, n, ld, e[j].f, beta, e[j].chromatic);
             break;
         case ORC_STAGE:
             if (apply_stage(z, n, ld, &e[j], ref)) return -1;

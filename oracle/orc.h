@@ -31,6 +31,9 @@ typedef struct {
     double f;          /* thin-lens focal length [m] */
     double n0_m3;      /* stage plasma density [m^-3] */
     double dE_MeV;     /* stage energy gain [MeV] */
+    double chirp;      /* stage: particle gain dE (1 + chirp t_entry), chirp [1/m]; 0 = uniform */
+    int32_t chromatic; /* quad, thin lens: focusing scales as 1/(1 + delta), first order in delta */
+    int32_t pad;
 } orc_elem;
 
 typedef struct {

@@ -30,7 +30,8 @@ def build(force: bool = True) -> str:
 class _Elem(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nsub", C.c_int32), ("L", C.c_double), ("k", C.c_double),
                 ("angle", C.c_double), ("f", C.c_double), ("n0_m3", C.c_double),
-                ("dE_MeV", C.c_double)]
+                ("dE_MeV", C.c_double), ("chirp", C.c_double), ("chromatic", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class _Ref(C.Structure):
@@ -134,9 +135,11 @@ def _elements(seq):
     for i, e in enumerate(seq):
         kind = e.kind if hasattr(e, "kind") else "stage"
         if kind == "stage" or not hasattr(e, "kind"):
-            arr[i] = _Elem(5, int(e.nsub), float(e.L), 0.0, 0.0, 0.0, float(e.n0_m3), float(e.dE_MeV))
+            arr[i] = _Elem(5, int(e.nsub), float(e.L), 0.0, 0.0, 0.0, float(e.n0_m3), float(e.dE_MeV),
+                           float(getattr(e, "chirp", 0.0)), 0, 0)
         else:
-            arr[i] = _Elem(_KIND[kind], 0, float(e.L), float(e.k), float(e.angle), float(e.f), 0.0, 0.0)
+            arr[i] = _Elem(_KIND[kind], 0, float(e.L), float(e.k), float(e.angle), float(e.f), 0.0, 0.0,
+                           0.0, int(bool(getattr(e, "chromatic", False))), 0)
     return arr
 
 

@@ -36,6 +36,7 @@ class Element:
     k: float = 0.0        # quadrupole strength [m^-2], k > 0 focuses x
     angle: float = 0.0    # bend angle [rad]
     f: float = 0.0        # thin-lens focal length [m]
+    chromatic: bool = False  # quad / thin lens: focusing scales with the particle's momentum
 
 
 @dataclass(frozen=True)
@@ -45,6 +46,7 @@ class Stage:
     n0_m3: float          # plasma electron density [m^-3]
     dE_MeV: float         # reference energy gain over the stage [MeV]
     nsub: int             # fine-step substeps
+    chirp: float = 0.0    # particle gain dE (1 + chirp t) with t its entry t [1/m]; 0 = uniform
 
 
 @dataclass(frozen=True)
