@@ -69,12 +69,19 @@ typedef struct hbl_ref {
 #define HBL_THIN_LENS 4
 #define HBL_STAGE 5
 
-/* One beamline element (host POD).  Fields not used by a kind are ignored.
+/* One beamline element (host POD).  Fields not used by a kind must be zero.
  *  DRIFT     L
- *  QUAD      L, k [m^-2] (k > 0 focuses x, defocuses y)
+ *  QUAD      L, k [m^-2] (k > 0 focuses x, defocuses y), chromatic
  *  SBEND     L, angle [rad] (sector bend, hard edge, no edge focusing)
- *  THIN_LENS f [m] (plasma lens: px -= x/f, py -= y/f; §4, Fig. 1)
- *  STAGE     L, n0_m3 [m^-3], dE_MeV, nsub (plasma stage, §4) */
+ *  THIN_LENS f [m] (plasma lens: px -= x/f, py -= y/f; §4, Fig. 1), chromatic
+ *  STAGE     L, n0_m3 [m^-3], dE_MeV, nsub (plasma stage, §4), chirp
+ * chromatic = 1: the focusing strength of a quad or lens scales as
+ *   1/(1 + delta) for a particle of relative momentum deviation delta,
+ *   taken to first order in delta = -pt/beta (drifts and px = dx/ds stay
+ *   those of the reference); 0: achromatic.  Other kinds reject 1.
+ * chirp [1/m]: a stage particle gains dE_MeV (1 + chirp t), t its entry
+ *   t (energy correlated along the bunch, as in the longitudinal correlation
+ *   of a plasma stage, §4.4); 0: uniform gain.  Other kinds reject nonzero. */
 typedef struct hbl_element {
     int32_t kind;
     int32_t nsub;
@@ -84,6 +91,9 @@ typedef struct hbl_element {
     double f;
     double n0_m3;
     double dE_MeV;
+    double chirp;
+    int32_t chromatic;
+    int32_t reserved;      /* must be 0 */
 } hbl_element;
 
 typedef void* hbl_stream;

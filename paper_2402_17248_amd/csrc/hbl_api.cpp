@@ -72,7 +72,9 @@ double* workspace(size_t bytes) {
     return g_ws[d];
 }
 
-// gamma_ref at the middle of each substep of a stage, cached per device.
+// gamma_ref at the middle of each substep of a stage, then the ramp increment
+// gp * s_mid of each substep (used by energy-correlated gain), cached per
+// device.
 static const double* stage_table(double g_in, double gp, double h, int32_t nsub, hbl_status* st) {
     const int d = current_device();
     if (d < 0 || d >= kMaxDev) {
@@ -84,16 +86,19 @@ static const double* stage_table(double g_in, double gp, double h, int32_t nsub,
     const StageKey key{g_in, gp, h, nsub};
     auto it = g_stage_tables[d].find(key);
     if (it != g_stage_tables[d].end()) return it->second;
-    std::vector<double> tab(nsub);
-    for (int32_t s = 0; s < nsub; ++s) tab[s] = g_in + gp * ((s + 0.5) * h);
+    std::vector<double> tab(2 * (size_t)nsub);
+    for (int32_t s = 0; s < nsub; ++s) {
+        tab[s] = g_in + gp * ((s + 0.5) * h);
+        tab[nsub + s] = gp * ((s + 0.5) * h);
+    }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(double) * nsub);
+    hipError_t e = hipMalloc(&p, sizeof(double) * 2 * nsub);
     if (e != hipSuccess) {
         *st = HBL_ENOMEM;
         set_error(HBL_ENOMEM, "stage table allocation failed: %s", hipGetErrorString(e));
         return nullptr;
     }
-    e = hipMemcpy(p, tab.data(), sizeof(double) * nsub, hipMemcpyHostToDevice);
+    e = hipMemcpy(p, tab.data(), sizeof(double) * 2 * nsub, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p);
         *st = HBL_EHIP;
@@ -175,7 +180,7 @@ double th_minus_sin(double th) {
 // motion over the element, for a reference of Lorentz factor gamma).
 }  // namespace
 
-GenCoef hbl::unify(int32_t kind, const ElemCoef& e) {
+GenCoef hbl::unify(int32_t kind, const ElemCoef& e, const double* chrom8) {
     GenCoef u;
     memset(&u, 0, sizeof u);
     double* g = u.g;
@@ -196,15 +201,45 @@ GenCoef hbl::unify(int32_t kind, const ElemCoef& e) {
             g[0] = 1.0; g[3] = c[0]; g[4] = 1.0; g[6] = 1.0; g[8] = c[0]; g[9] = 1.0;
             break;
     }
+    if (chrom8)
+        for (int q = 0; q < 8; ++q) g[16 + q] = chrom8[q];
     return u;
 }
 
 namespace {
 
-hbl_status compile_element(const hbl_element& e, double gamma, int32_t* kind, ElemCoef* c) {
+// First-order chromatic terms of a focusing plane [[a, b], [c, a]] of strength
+// k: the particle sees k (1 - delta) to first order, so with w = sqrt|k| the
+// entries change by delta times their derivative along dw/d(delta) = -w/2.
+void plane_derivative(bool focusing, double w, double L, double* da, double* db, double* dc) {
+    const double ph = w * L;
+    if (focusing) {
+        const double sn = sin(ph), cs = cos(ph);
+        *da = 0.5 * ph * sn;
+        *db = 0.5 * (sn / w - L * cs);
+        *dc = 0.5 * w * (sn + ph * cs);
+    } else {
+        const double sh = sinh(ph), ch = cosh(ph);
+        *da = -0.5 * ph * sh;
+        *db = 0.5 * (sh / w - L * ch);
+        *dc = -0.5 * w * (sh + ph * ch);
+    }
+}
+
+// chrom8 receives the chromatic coefficients (the factors of pt, with
+// delta = -pt/beta) when the element is chromatic; *chromatic says so.
+hbl_status compile_element(const hbl_element& e, double gamma, int32_t* kind, ElemCoef* c, double chrom8[8],
+                           bool* chromatic) {
     memset(c, 0, sizeof *c);
+    for (int q = 0; q < 8; ++q) chrom8[q] = 0.0;
+    *chromatic = false;
     const double bg = sqrt(gamma * gamma - 1.0), beta = bg / gamma;
     const double r56d = e.L / (bg * bg);
+    HBL_REQUIRE(e.reserved == 0, "reserved field must be 0");
+    HBL_REQUIRE(e.chirp == 0.0, "chirp applies to stages only");
+    HBL_REQUIRE(e.chromatic == 0 || e.chromatic == 1, "chromatic must be 0 or 1");
+    HBL_REQUIRE(e.chromatic == 0 || e.kind == HBL_QUAD || e.kind == HBL_THIN_LENS,
+                "chromatic applies to quads and thin lenses only");
     switch (e.kind) {
         case HBL_DRIFT:
             HBL_REQUIRE(isfinite(e.L), "drift: L must be finite");
@@ -228,6 +263,15 @@ hbl_status compile_element(const hbl_element& e, double gamma, int32_t* kind, El
             c->c[0] = xf ? fc : dc; c->c[1] = xf ? fs : ds; c->c[2] = xf ? fm : dm; c->c[3] = xf ? fc : dc;
             c->c[4] = xf ? dc : fc; c->c[5] = xf ? ds : fs; c->c[6] = xf ? dm : fm; c->c[7] = xf ? dc : fc;
             c->c[8] = r56d;
+            if (e.chromatic) {
+                double ax, bx, cx, ay, by, cy;
+                plane_derivative(xf, w, e.L, &ax, &bx, &cx);
+                plane_derivative(!xf, w, e.L, &ay, &by, &cy);
+                const double m = -1.0 / beta;       // d(delta)/d(pt)
+                chrom8[0] = m * ax; chrom8[1] = m * bx; chrom8[2] = m * cx; chrom8[3] = m * ax;
+                chrom8[4] = m * ay; chrom8[5] = m * by; chrom8[6] = m * cy; chrom8[7] = m * ay;
+                *chromatic = true;
+            }
             return HBL_OK;
         }
         case HBL_SBEND: {
@@ -259,6 +303,11 @@ hbl_status compile_element(const hbl_element& e, double gamma, int32_t* kind, El
             HBL_REQUIRE(isfinite(e.f) && e.f != 0.0, "thin lens: f must be finite and nonzero");
             *kind = kLens;
             c->c[0] = -1.0 / e.f;
+            if (e.chromatic) {      // kick c0 x (1 - delta) = c0 x + (c0 / beta) x pt
+                chrom8[2] = c->c[0] / beta;
+                chrom8[6] = c->c[0] / beta;
+                *chromatic = true;
+            }
             return HBL_OK;
         case HBL_STAGE:
             set_error(HBL_EINVAL, "a lattice holds linear elements only; apply stages with hbl_apply_stage");
@@ -279,6 +328,7 @@ struct hbl_lattice {
     int32_t* d_kinds;
     double* d_coef;   // one allocation: n GenCoef records, then n ElemCoef records
     double* d_gen;
+    bool chromatic;   // any chromatic element
     std::vector<int32_t> kinds;
     std::vector<ElemCoef> coef;
 };
@@ -314,9 +364,16 @@ hbl_status hbl_lattice_create(const hbl_element* elems, int32_t n_elem, const hb
     if (hbl_status st = check_ref(ref)) return st;
     std::vector<int32_t> kinds(n_elem);
     std::vector<ElemCoef> coef(n_elem);
+    std::vector<double> chrom(8 * (size_t)n_elem);
+    std::vector<char> is_chrom(n_elem);
+    bool any_chrom = false;
     double length = 0.0;
     for (int32_t i = 0; i < n_elem; ++i) {
-        if (hbl_status st = compile_element(elems[i], ref->gamma, &kinds[i], &coef[i])) {
+        bool ch = false;
+        hbl_status st = compile_element(elems[i], ref->gamma, &kinds[i], &coef[i], &chrom[8 * (size_t)i], &ch);
+        is_chrom[i] = ch;
+        any_chrom = any_chrom || ch;
+        if (st) {
             char msg[512];
             snprintf(msg, sizeof msg, "%s", g_err);
             set_error(st, "element %d: %s", (int)i, msg);
@@ -334,6 +391,7 @@ hbl_status hbl_lattice_create(const hbl_element* elems, int32_t n_elem, const hb
     lat->d_kinds = nullptr;
     lat->d_coef = nullptr;
     lat->d_gen = nullptr;
+    lat->chromatic = any_chrom;
     if (hipGetDevice(&lat->device) != hipSuccess) {
         delete lat;
         set_error(HBL_EHIP, "lattice_create: no HIP device");
@@ -342,7 +400,8 @@ hbl_status hbl_lattice_create(const hbl_element* elems, int32_t n_elem, const hb
     if (n_elem > 0) {
         void *pk = nullptr, *pc = nullptr;
         std::vector<GenCoef> gen((size_t)n_elem);
-        for (int32_t i = 0; i < n_elem; ++i) gen[i] = unify(kinds[i], coef[i]);
+        for (int32_t i = 0; i < n_elem; ++i)
+            gen[i] = unify(kinds[i], coef[i], is_chrom[i] ? &chrom[8 * (size_t)i] : nullptr);
         const size_t gen_bytes = sizeof(GenCoef) * n_elem;
         if (hipMalloc(&pk, sizeof(int32_t) * n_elem) != hipSuccess ||
             hipMalloc(&pc, gen_bytes + sizeof(ElemCoef) * n_elem) != hipSuccess) {
@@ -398,7 +457,10 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
     if (n > 0 && lat->n_elem > 0) {
         hipStream_t s = (hipStream_t)stream;
         if (flags == HBL_FUSED) {
-            HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_gen, lat->n_elem, s));
+            HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_gen, lat->n_elem, lat->chromatic, s));
+        } else if (lat->chromatic) {   // one launch per element, through its unified record
+            for (int32_t i = 0; i < lat->n_elem; ++i)
+                HBL_HIP(launch_lattice_gen(z, n, ld, lat->d_gen + (size_t)kGen * i, true, s));
         } else {
             for (int32_t i = 0; i < lat->n_elem; ++i)
                 HBL_HIP(launch_lattice_element(z, n, ld, lat->kinds[i], lat->coef[i], s));
@@ -413,12 +475,13 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
 namespace {
 
 LatticeView view_of(const hbl_lattice* lat) {
-    LatticeView v{nullptr, nullptr, nullptr, 0};
+    LatticeView v{nullptr, nullptr, nullptr, 0, 0};
     if (lat) {
         v.kinds = lat->d_kinds;
         v.coef = lat->d_coef;
         v.gen = lat->d_gen;
         v.n = lat->n_elem;
+        v.chromatic = lat->chromatic ? 1 : 0;
     }
     return v;
 }
@@ -442,6 +505,8 @@ hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
     HBL_REQUIRE(finite_pos(stage->L), "apply_stage: L must be finite and > 0");
     HBL_REQUIRE(isfinite(stage->n0_m3) && stage->n0_m3 >= 0.0, "apply_stage: n0 must be finite and >= 0");
     HBL_REQUIRE(isfinite(stage->dE_MeV), "apply_stage: dE must be finite");
+    HBL_REQUIRE(isfinite(stage->chirp), "apply_stage: chirp must be finite");
+    HBL_REQUIRE(stage->chromatic == 0 && stage->reserved == 0, "apply_stage: chromatic/reserved must be 0 for a stage");
     if (hbl_status st = check_ref(ref)) return st;
     const double g_in = ref->gamma;
     const double g_out = g_in + stage->dE_MeV / ref->mass_MeV;
@@ -469,6 +534,10 @@ hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
     p.pt_scale = bg_in / bg_out;
     p.r56 = (gp == 0.0) ? bg_in * L / (g_in * g_in * g_in)
                         : bg_in * (1.0 / (g_in * g_in) - 1.0 / (g_out * g_out)) / (2.0 * gp);
+    p.chirp = stage->chirp;
+    p.chirp_gain = stage->chirp * (g_out - g_in);
+    p.chirp_t = stage->chirp * (gp * L * L / (2.0 * g_in * g_out * g_out));
+    p.inv_bgout = 1.0 / bg_out;
     p.nsub = N;
     // Newton steps for 1/gamma_i from the previous substep: the relative
     // change per substep is at most d = |gp h| / gamma_min, with particle
@@ -488,7 +557,8 @@ hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
         }
         if (err >= 1e-17) newton = 0;
     }
-    p.newton = newton;
+    // with a chirp the particle's own ramp rate is unbounded a priori: divide
+    p.newton = stage->chirp != 0.0 ? 0 : newton;
     hbl_status st = HBL_OK;
     if (n > 0) {
         const double* tab = stage_table(g_in, gp, h, N, &st);

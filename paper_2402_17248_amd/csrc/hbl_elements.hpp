@@ -43,7 +43,9 @@ __device__ __forceinline__ void el_lens(P6& p, const double* c) {
 }
 
 // Any element through its unified record (GenCoef): branch-free, bitwise
-// equal to the specialised map of its kind.
+// equal to the specialised map of its kind; CHROM adds the first-order
+// chromatic terms of quads and lenses (zero for the other kinds).
+template <bool CHROM = false>
 __device__ __forceinline__ void el_unified(P6& p, const double* g) {
     const double x = p.x, px = p.px, y = p.y, py = p.py, pt = p.pt;
     p.x = fma(g[2], pt, fma(g[1], px, g[0] * x));
@@ -51,6 +53,12 @@ __device__ __forceinline__ void el_unified(P6& p, const double* g) {
     p.y = fma(g[7], py, g[6] * y);
     p.py = fma(g[9], py, g[8] * y);
     p.t = fma(g[12], pt, fma(g[11], px, fma(g[10], x, p.t)));
+    if (CHROM) {
+        p.x = fma(fma(g[17], px, g[16] * x), pt, p.x);
+        p.px = fma(fma(g[19], px, g[18] * x), pt, p.px);
+        p.y = fma(fma(g[21], py, g[20] * y), pt, p.y);
+        p.py = fma(fma(g[23], py, g[22] * y), pt, p.py);
+    }
 }
 
 // A compiled element sequence (device coefficient tables), passed by value.
@@ -59,12 +67,14 @@ struct LatticeView {
     const double* coef;   // ElemCoef records
     const double* gen;    // GenCoef records
     int32_t n;
+    int32_t chromatic;    // any element chromatic
 };
 
 // Apply the sequence to one particle: the unified record of each element,
 // read by scalar loads (uniform across the wavefront), no branches.
+template <bool CHROM = false>
 __device__ __forceinline__ void apply_elements(P6& p, const LatticeView& lv) {
-    for (int32_t e = 0; e < lv.n; ++e) el_unified(p, lv.gen + (int64_t)e * kGen);
+    for (int32_t e = 0; e < lv.n; ++e) el_unified<CHROM>(p, lv.gen + (int64_t)e * kGen);
 }
 
 __device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {

@@ -36,12 +36,17 @@ struct ElemCoef {
 //   t'  = fma(g12, pt, fma(g11, px, fma(g10, x, t)))
 // with unit and zero coefficients placed so that every kind gives exactly
 // the same result as its specialised map (a multiply by 1, an fma with a 0
-// factor and an fma adding +-0 are exact).  16 doubles, 3 unused.
-constexpr int kGen = 16;
+// factor and an fma adding +-0 are exact).  Chromatic quads and lenses add,
+// with the old coordinates and pt (first order in delta = -pt/beta),
+//   x'  = fma(fma(g17, px, g16 * x), pt, x'),  px' = fma(fma(g19, px, g18 * x), pt, px')
+//   y'  = fma(fma(g21, py, g20 * y), pt, y'),  py' = fma(fma(g23, py, g22 * y), pt, py')
+// 24 doubles, 13..15 unused.
+constexpr int kGen = 24;
 struct GenCoef {
     double g[kGen];
 };
-GenCoef unify(int32_t kind, const ElemCoef& c);
+// chrom8: the eight chromatic coefficients (g16..g23) or nullptr.
+GenCoef unify(int32_t kind, const ElemCoef& c, const double* chrom8);
 
 // ----------------------------------------------------------- stage params
 struct StageParams {
@@ -52,6 +57,11 @@ struct StageParams {
     double inv_h_bgout;    // 1/(h (beta gamma)_out)
     double pt_scale;       // (beta gamma)_in / (beta gamma)_out
     double r56;            // first-order flight-time coefficient
+    // energy-correlated gain (chirp != 0): particle gain dE (1 + chirp t_entry)
+    double chirp;          // [1/m]
+    double chirp_gain;     // chirp (gamma_out - gamma_in)
+    double chirp_t;        // chirp gp L^2 / (2 gamma_in gamma_out^2)
+    double inv_bgout;      // 1/(beta gamma)_out
     int32_t nsub;
     int32_t newton;        // Newton steps per substep (0 = divide every substep)
 };
@@ -63,12 +73,17 @@ hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
                                 const double* mean, const double* sigma, int64_t i0,
                                 hipStream_t s);
 hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, int32_t n_elem,
-                                hipStream_t s);
+                                bool chromatic, hipStream_t s);
+// One element through its unified record (unfused push of a chromatic lattice).
+hipError_t launch_lattice_gen(double* z, int64_t n, int64_t ld, const double* gen1, bool chromatic,
+                              hipStream_t s);
 hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind,
                                   const ElemCoef& c, hipStream_t s);
 struct LatticeView;
+// tab: gamma_ref at the middle of each substep, then (chirp only) the ramp
+// increment gp * s_mid of each substep.
 hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
-                        const StageParams& p, const double* gmid, const LatticeView& pre,
+                        const StageParams& p, const double* tab, const LatticeView& pre,
                         const LatticeView& post, hipStream_t s);
 
 // Reductions.  `ws` is device scratch of at least reduce_ws_bytes(n) bytes.

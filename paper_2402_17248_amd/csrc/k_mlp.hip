@@ -252,7 +252,7 @@ constexpr int kInferBlock = 256;
 // layer-0 operand of each tile from that tile's owner lanes, and after the
 // network each owner gathers its six outputs (rows 0-3 live in lane group 0,
 // rows 4-5 in lane group 1) -- cross-lane moves only, no redundant loads.
-template <bool GAPS>
+template <bool GAPS, bool CHROM = false>
 __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(
     double* __restrict__ z, int64_t n, int64_t ld, const uint32_t* __restrict__ img, NormArgs na,
     LatticeView pre, LatticeView post) {
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
         P6 p;
         if (live) load6(z, ld, i, p);
         else p = P6{na.mu_in[0], na.mu_in[1], na.mu_in[2], na.mu_in[3], na.mu_in[4], na.mu_in[5]};
-        if (GAPS) apply_elements(p, pre);
+        if (GAPS) apply_elements<CHROM>(p, pre);
         const double pv[6] = {p.x, p.y, p.t, p.px, p.py, p.pt};
         uint32_t hw[3], lw[3];
 #pragma unroll
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
         q.px = fma(na.sd_out[3], (double)o[3], na.mu_out[3]);
         q.py = fma(na.sd_out[4], (double)o[4], na.mu_out[4]);
         q.pt = fma(na.sd_out[5], (double)o[5], na.mu_out[5]);
-        if (GAPS) apply_elements(q, post);
+        if (GAPS) apply_elements<CHROM>(q, post);
         if (live) store6(z, ld, i, q);
     }
 }
@@ -761,7 +761,10 @@ hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* im
     int64_t blocks = (groups + 3) / 4;
     const int64_t cap = 256 * 2;  // persistent: two 4-wave blocks per CU
     if (blocks > cap) blocks = cap;
-    if (pre.n > 0 || post.n > 0)
+    if ((pre.n > 0 && pre.chromatic) || (post.n > 0 && post.chromatic))
+        hipLaunchKernelGGL((k_mlp_infer<true, true>), dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld,
+                           img, na, pre, post);
+    else if (pre.n > 0 || post.n > 0)
         hipLaunchKernelGGL(k_mlp_infer<true>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na,
                            pre, post);
     else

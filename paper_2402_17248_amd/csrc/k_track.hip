@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z
 // kinds cost more in register copies than the unified form's extra FMAs.
 constexpr int kPer = 2;
 
+template <bool CHROM>
 __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z, int64_t n,
                                                           int64_t ld, const double* __restrict__ gen,
                                                           int32_t n_elem) {
@@ -126,13 +127,27 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
         for (int32_t e = 0; e < n_elem; ++e) {
             const double* g = gen + (int64_t)e * kGen;
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) el_unified(p[k], g);
+            for (int k = 0; k < kPer; ++k) el_unified<CHROM>(p[k], g);
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = base + k * kBlock + threadIdx.x;
             if (live[k]) store6(z, ld, i, p[k]);
         }
+    }
+}
+
+// One element through its unified record: the unfused push of a lattice
+// with chromatic elements (the specialised kernels below are achromatic).
+template <bool CHROM>
+__global__ __launch_bounds__(kBlock) void k_lattice_gen(double* __restrict__ z, int64_t n, int64_t ld,
+                                                        const double* __restrict__ g) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        P6 p;
+        load6(z, ld, i, p);
+        el_unified<CHROM>(p, g);
+        store6(z, ld, i, p);
     }
 }
 
@@ -188,32 +203,36 @@ __global__ __launch_bounds__(kBlock) void k_lattice_one(double* __restrict__ z, 
 // The transport gap before the stage (pre) and after it (post) are applied
 // in registers in the same pass (empty sequences for a lone stage), and the
 // recorded training input is the state after `pre`.
-template <int NEWTON>
+template <int NEWTON, bool CHIRP, bool CHROM>
 __global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_t n, int64_t ld,
                                                   double* __restrict__ rec, int64_t rld,
                                                   StageParams sp,
                                                   const double* __restrict__ gmid,
                                                   LatticeView pre, LatticeView post) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const double* __restrict__ gs = gmid + sp.nsub;   // gp * s_mid per substep (CHIRP)
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
         P6 p;
         load6(z, ld, i, p);
-        apply_elements(p, pre);
+        apply_elements<CHROM>(p, pre);
         if (rec) store6(rec, rld, i, p);
+        const double t_in = p.t;
         const double dg = -p.pt * sp.bg_in;
+        // particle gradient gp (1 + chirp t_in): gamma_i = gamma_mid + dg + chirp t_in gp s_mid
+        const double cg = CHIRP ? sp.chirp * t_in : 0.0;
         const double hb = sp.h * sp.bg_in;
         double x = p.x, y = p.y;
         double vx = p.px * hb, vy = p.py * hb;
         vx = fma(-sp.half_hk2, x, vx);
         vy = fma(-sp.half_hk2, y, vy);
-        double a = gmid[0] + dg;
+        double a = CHIRP ? fma(cg, gs[0], gmid[0] + dg) : gmid[0] + dg;
         double r = 1.0 / a;
         x = fma(vx, r, x);
         y = fma(vy, r, y);
         for (int32_t s = 1; s < sp.nsub; ++s) {
             vx = fma(-sp.hk2, x, vx);
             vy = fma(-sp.hk2, y, vy);
-            a = gmid[s] + dg;
+            a = CHIRP ? fma(cg, gs[s], gmid[s] + dg) : gmid[s] + dg;
             if (NEWTON == 0) {
                 r = 1.0 / a;
             } else {
@@ -233,8 +252,13 @@ __global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_
         p.px = vx * sp.inv_h_bgout;
         p.py = vy * sp.inv_h_bgout;
         p.t = fma(sp.r56, p.pt, p.t);
-        p.pt = p.pt * sp.pt_scale;
-        apply_elements(p, post);
+        if (CHIRP) {
+            p.t = fma(-sp.chirp_t, t_in, p.t);
+            p.pt = fma(-sp.chirp_gain, t_in, p.pt * sp.bg_in) * sp.inv_bgout;
+        } else {
+            p.pt = p.pt * sp.pt_scale;
+        }
+        apply_elements<CHROM>(p, post);
         store6(z, ld, i, p);
     }
 }
@@ -264,10 +288,24 @@ hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
 }
 
 hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, int32_t n_elem,
-                                hipStream_t s) {
+                                bool chromatic, hipStream_t s) {
     if (n == 0 || n_elem == 0) return hipSuccess;
     const int grid = grid_for(n, (int64_t)kPer * kBlock, 1 << 20);
-    hipLaunchKernelGGL(k_lattice_fused, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, n_elem);
+    if (chromatic)
+        hipLaunchKernelGGL(k_lattice_fused<true>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, n_elem);
+    else
+        hipLaunchKernelGGL(k_lattice_fused<false>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, n_elem);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_gen(double* z, int64_t n, int64_t ld, const double* gen1, bool chromatic,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(n, kBlock, 1 << 20);
+    if (chromatic)
+        hipLaunchKernelGGL(k_lattice_gen<true>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen1);
+    else
+        hipLaunchKernelGGL(k_lattice_gen<false>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen1);
     return hipGetLastError();
 }
 
@@ -292,15 +330,15 @@ hipError_t launch_lattice_element(double* z, int64_t n, int64_t ld, int32_t kind
     return hipGetLastError();
 }
 
-hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
-                        const StageParams& p, const double* gmid, const LatticeView& pre,
-                        const LatticeView& post, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const int grid = grid_for(n, kBlock, 1 << 20);
-#define HBL_STAGE_LAUNCH(K)                                                                        \
-    hipLaunchKernelGGL(k_stage<K>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, p, gmid, pre, \
-                       post)
-    switch (p.newton) {
+namespace {
+template <bool CHIRP, bool CHROM>
+void launch_stage_t(int grid, double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
+                    const StageParams& p, const double* tab, const LatticeView& pre,
+                    const LatticeView& post, hipStream_t s) {
+#define HBL_STAGE_LAUNCH(K)                                                                         \
+    hipLaunchKernelGGL((k_stage<K, CHIRP, CHROM>), dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, \
+                       p, tab, pre, post)
+    switch (CHIRP ? 0 : p.newton) {
         case 1: HBL_STAGE_LAUNCH(1); break;
         case 2: HBL_STAGE_LAUNCH(2); break;
         case 3: HBL_STAGE_LAUNCH(3); break;
@@ -308,6 +346,19 @@ hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t r
         default: HBL_STAGE_LAUNCH(0); break;
     }
 #undef HBL_STAGE_LAUNCH
+}
+}  // namespace
+
+hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t rld,
+                        const StageParams& p, const double* tab, const LatticeView& pre,
+                        const LatticeView& post, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int grid = grid_for(n, kBlock, 1 << 20);
+    const bool chirp = p.chirp != 0.0, chrom = pre.chromatic || post.chromatic;
+    if (chirp && chrom) launch_stage_t<true, true>(grid, z, n, ld, rec, rld, p, tab, pre, post, s);
+    else if (chirp) launch_stage_t<true, false>(grid, z, n, ld, rec, rld, p, tab, pre, post, s);
+    else if (chrom) launch_stage_t<false, true>(grid, z, n, ld, rec, rld, p, tab, pre, post, s);
+    else launch_stage_t<false, false>(grid, z, n, ld, rec, rld, p, tab, pre, post, s);
     return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ class HblError(RuntimeError):
 
 class Element(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nsub", C.c_int32), ("L", C.c_double), ("k", C.c_double),
-                ("angle", C.c_double), ("f", C.c_double), ("n0_m3", C.c_double), ("dE_MeV", C.c_double)]
+                ("angle", C.c_double), ("f", C.c_double), ("n0_m3", C.c_double), ("dE_MeV", C.c_double),
+                ("chirp", C.c_double), ("chromatic", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Ref(C.Structure):
@@ -150,8 +151,10 @@ def _bunch_args(z, n=None):
 def element(e) -> Element:
     """From a workloads.Element / workloads.Stage description."""
     if hasattr(e, "kind"):
-        return Element(_KIND[e.kind], 0, float(e.L), float(e.k), float(e.angle), float(e.f), 0.0, 0.0)
-    return Element(STAGE, int(e.nsub), float(e.L), 0.0, 0.0, 0.0, float(e.n0_m3), float(e.dE_MeV))
+        return Element(_KIND[e.kind], 0, float(e.L), float(e.k), float(e.angle), float(e.f), 0.0, 0.0, 0.0,
+                       int(bool(getattr(e, "chromatic", False))), 0)
+    return Element(STAGE, int(e.nsub), float(e.L), 0.0, 0.0, 0.0, float(e.n0_m3), float(e.dE_MeV),
+                   float(getattr(e, "chirp", 0.0)), 0, 0)
 
 
 # ------------------------------------------------------------------ verbs

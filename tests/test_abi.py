@@ -72,6 +72,10 @@ def _lat(hbl, elems, gamma=1957.0):
     (dict(kind=2, L=1.0, k=float("nan")), "finite"),
     (dict(kind=3, L=0.0, angle=0.1), "nonzero length"),
     (dict(kind=5, L=0.3, nsub=10), "linear elements only"),
+    (dict(kind=1, L=1.0, chromatic=1), "quads and thin lenses only"),
+    (dict(kind=2, L=1.0, k=1.0, chromatic=2), "chromatic must be 0 or 1"),
+    (dict(kind=2, L=1.0, k=1.0, chirp=1.0), "stages only"),
+    (dict(kind=4, f=1.0, reserved=1), "reserved"),
 ])
 def test_lattice_rejects_bad_elements(hbl, el, frag):
     rc = _lat(hbl, [hbl.Element(**el)])
@@ -90,6 +94,8 @@ def test_lattice_rejects_bad_reference(hbl):
     (dict(kind=5, L=-0.3, nsub=10), "L must be"),
     (dict(kind=5, L=0.3, nsub=10, n0_m3=-1.0), "n0"),
     (dict(kind=5, L=0.3, nsub=10, dE_MeV=-2000.0), "exit gamma"),
+    (dict(kind=5, L=0.3, nsub=10, chirp=float("nan")), "chirp"),
+    (dict(kind=5, L=0.3, nsub=10, chromatic=1), "chromatic/reserved"),
 ])
 def test_stage_rejects_bad_parameters(hbl, st, frag):
     el = hbl.Element(**st)

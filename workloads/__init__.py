@@ -88,9 +88,10 @@ def chicane(L_bend=0.5, angle=5e-3, L_drift=1.0) -> List[Element]:
             sbend(L_bend, -angle), drift(L_drift), sbend(L_bend, +angle)]
 
 
-def triplet() -> List[Element]:
+def triplet(chromatic: bool = False) -> List[Element]:
     """Matching quad triplet around a stage: Q(+2) D0.2 Q(-2) D0.2 Q(+2), quads 0.3 m."""
-    return [quad(0.3, +2.0), drift(0.2), quad(0.3, -2.0), drift(0.2), quad(0.3, +2.0)]
+    q = lambda k: Element(QUAD, L=0.3, k=k, chromatic=chromatic)
+    return [q(+2.0), drift(0.2), q(-2.0), drift(0.2), q(+2.0)]
 
 
 # Interstage triplet strengths (m^-2): with the drifts of interstage(), the
@@ -141,10 +142,24 @@ def c2_fused(n=1_000_000, seed=2) -> Workload:
                     "10 FODO + chicane + thin lens (58 elements), fused vs unfused")
 
 
+# Energy-correlated gain of the chromatic variant: 1 % more gain per 200 um
+# of t (the bunch is 10 um long, so +-1.5e-3 of the gain over +-3 sigma).
+C3_CHIRP_PER_M = 50.0
+
+
 def c3_stage(n=1_000_000, seed=13, nsub=2000) -> Workload:
     return Workload("stage_1to10GeV_1e6", BunchSpec(n, seed), E0_MeV,
                     [triplet(), plasma_stage(9000.0, nsub), triplet()],
                     "triplet + fine-step stage 1->10 GeV + triplet")
+
+
+def c3_chromatic(n=1_000_000, seed=13, nsub=2000, chirp=C3_CHIRP_PER_M) -> Workload:
+    """C3 with energy-dependent optics: chromatic triplets and a stage whose
+    gain varies linearly along the bunch (gain dE (1 + chirp t))."""
+    st = Stage(L=0.3, n0_m3=1e23, dE_MeV=9000.0, nsub=nsub, chirp=chirp)
+    return Workload("stage_chromatic_1to10GeV_1e6", BunchSpec(n, seed), E0_MeV,
+                    [triplet(True), st, triplet(True)],
+                    "chromatic triplet + chirped fine-step stage 1->10 GeV + chromatic triplet")
 
 
 C3_PAIR_SEED = 3
