@@ -180,19 +180,22 @@ def cpu_baseline(wl, chain, budget_s):
             "serial_value": m1 / t1, "serial_sample": f"first {m1} particles on one core, {t1:.1f} s"}
 
 
-def single_stage_study(args, log):
+def single_stage_study(args, log, chromatic=False):
     """C4: the 1 -> 10 GeV stage behind its entrance triplet.  A surrogate is
     trained on 2^20 pairs of the fine-step stage (seed 3) and applied to a
     fresh 1e7-particle bunch (seed 4); accuracy and speed against the
     2000-substep stage, and against the fine-step stage at the substep count
     whose emittance error (vs a 32,000-substep reference) equals the
-    surrogate's."""
+    surrogate's.  chromatic: the same on the variant with chromatic triplets
+    and an energy-correlated stage gain."""
+    import dataclasses
+
     import torch
 
     import workloads as W
     from paper_2402_17248_amd import hbl
 
-    wl = W.c3_stage()
+    wl = W.c3_chromatic() if chromatic else W.c3_stage()
     sig = wl.bunch.sigma
     stage = wl.beamline[1]
 
@@ -232,14 +235,15 @@ def single_stage_study(args, log):
     m = 1_000_000
     xm = x[:, :m].contiguous()
     conv = xm.clone()
-    hbl.apply_stage(conv, hbl.Element(5, 32000, stage.L, 0, 0, 0, stage.n0_m3, stage.dE_MeV), r0.copy(), n=m)
+    with_nsub = lambda k: hbl.element(dataclasses.replace(stage, nsub=k))
+    hbl.apply_stage(conv, with_nsub(32000), r0.copy(), n=m)
     sm = xm.clone()
     sur.apply(sm, r0.copy(), n=m)
     err_s = max(abs(e) for e in hbl.compare(sm, conv, n=m)[2][:2])
 
     def err_fine(nsub):
         fm = xm.clone()
-        hbl.apply_stage(fm, hbl.Element(5, nsub, stage.L, 0, 0, 0, stage.n0_m3, stage.dE_MeV), r0.copy(), n=m)
+        hbl.apply_stage(fm, with_nsub(nsub), r0.copy(), n=m)
         return max(abs(e) for e in hbl.compare(fm, conv, n=m)[2][:2])
 
     lo, hi = 50, 32000
@@ -252,17 +256,18 @@ def single_stage_study(args, log):
         else:
             lo = mid
     n_eq = hi
-    el_eq = hbl.Element(5, n_eq, stage.L, 0, 0, 0, stage.n0_m3, stage.dE_MeV)
+    el_eq = with_nsub(n_eq)
     f2 = x.clone()
     t_fine_eq = time_events(torch, lambda: hbl.apply_stage(f2, el_eq, r0.copy(), n=N), 3)
-    out = {"workload": "stage_1to10GeV_1e7", "particles": N, "epochs": args.epochs,
+    out = {"workload": ("stage_chromatic_1to10GeV_1e7" if chromatic else "stage_1to10GeV_1e7"),
+           "particles": N, "epochs": args.epochs,
            "train_seconds": t_train, "final_loss_train_test": [float(v) for v in curve[-1]],
            "eps_rel_xyt_vs_2000_substeps": eps, "rms_over_sigma": rms, "centroid_over_sigma": cen,
            "inference_ms": t_inf * 1e3, "fine_step_2000_ms": t_fine * 1e3, "speedup_vs_2000": t_fine / t_inf,
            "eps_err_vs_converged_32000": {"surrogate": err_s, "fine_step_at_equal_error_nsub": n_eq},
            "fine_step_equal_error_ms": t_fine_eq * 1e3, "speedup_at_equal_error": t_fine_eq / t_inf,
            "inference_particles_per_s": N / t_inf}
-    log(f"C4 single stage: eps_rel {eps}, rms {rms}; inference {t_inf*1e3:.3f} ms vs fine-step "
+    log(f"{'chromatic ' if chromatic else ''}C4 single stage: eps_rel {eps}, rms {rms}; inference {t_inf*1e3:.3f} ms vs fine-step "
         f"{t_fine*1e3:.3f} ms ({t_fine/t_inf:.1f}x); equal-error fine-step nsub {n_eq} "
         f"({t_fine_eq*1e3:.3f} ms, {t_fine_eq/t_inf:.1f}x)")
     return out, t_inf
@@ -491,9 +496,10 @@ def main():
         equal = chain_equal_error(args, wl, chain, dt_sur, time_chain, log)
         configs = config_studies(log)
 
-    single = None
+    single = single_chrom = None
     if not args.no_single_stage:
         single, _ = single_stage_study(args, log)
+        single_chrom, _ = single_stage_study(args, log, chromatic=True)
 
     # ---- dominant kernel: surrogate inference with the gaps fused (k_mlp_infer,
     # one launch per stage pass), timed inside the timed steps above
@@ -531,6 +537,7 @@ def main():
         "chain_equal_error": equal,
         "other_configs": configs,
         "single_stage_c4": single,
+        "single_stage_c4_chromatic": single_chrom,
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
         "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,
                      "unit": "T VALU slots/s", "frac": alu_achieved / VALU_PEAK_TSLOTS,

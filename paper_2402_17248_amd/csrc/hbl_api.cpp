@@ -544,8 +544,10 @@ hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
     // energy offsets |dgamma_i| up to 10% of the reference (a linear-optics
     // beam stays far inside); k steps reduce it to d^(2^k); require < 1e-17,
     // else divide every substep.
+    // With a chirp the particle's ramp rate is gp (1 + chirp t): sized here for
+    // |chirp t| <= 1; the kernel divides for a particle beyond that.
     const double gmin = fmin(g_in, g_out) * 0.9;
-    const double d = fabs(gp * h) / gmin;
+    const double d = fabs(gp * h) * (stage->chirp != 0.0 ? 2.0 : 1.0) / gmin;
     int newton = 0;
     if (d < 0.25) {
         double err = d;
@@ -557,8 +559,7 @@ hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
         }
         if (err >= 1e-17) newton = 0;
     }
-    // with a chirp the particle's own ramp rate is unbounded a priori: divide
-    p.newton = stage->chirp != 0.0 ? 0 : newton;
+    p.newton = newton;
     hbl_status st = HBL_OK;
     if (n > 0) {
         const double* tab = stage_table(g_in, gp, h, N, &st);

@@ -220,6 +220,9 @@ __global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_
         const double dg = -p.pt * sp.bg_in;
         // particle gradient gp (1 + chirp t_in): gamma_i = gamma_mid + dg + chirp t_in gp s_mid
         const double cg = CHIRP ? sp.chirp * t_in : 0.0;
+        // the host sized the Newton steps for a gain factor 1 + chirp t within [0, 2];
+        // a particle outside divides (a per-lane branch, uniform in practice)
+        const bool divide = CHIRP && fabs(cg) > 1.0;
         const double hb = sp.h * sp.bg_in;
         double x = p.x, y = p.y;
         double vx = p.px * hb, vy = p.py * hb;
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(double* __restrict__ z, int64_
             vx = fma(-sp.hk2, x, vx);
             vy = fma(-sp.hk2, y, vy);
             a = CHIRP ? fma(cg, gs[s], gmid[s] + dg) : gmid[s] + dg;
-            if (NEWTON == 0) {
+            if (NEWTON == 0 || divide) {
                 r = 1.0 / a;
             } else {
 #pragma unroll
@@ -338,7 +341,7 @@ void launch_stage_t(int grid, double* z, int64_t n, int64_t ld, double* rec, int
 #define HBL_STAGE_LAUNCH(K)                                                                         \
     hipLaunchKernelGGL((k_stage<K, CHIRP, CHROM>), dim3(grid), dim3(kBlock), 0, s, z, n, ld, rec, rld, \
                        p, tab, pre, post)
-    switch (CHIRP ? 0 : p.newton) {
+    switch (p.newton) {
         case 1: HBL_STAGE_LAUNCH(1); break;
         case 2: HBL_STAGE_LAUNCH(2); break;
         case 3: HBL_STAGE_LAUNCH(3); break;

@@ -129,3 +129,20 @@ def test_surrogate_with_chromatic_gaps_bitwise(hbl, orc):
     post.push(zb, post_ref.copy(), n=n)
     torch.cuda.synchronize()
     assert torch.equal(za, zb)
+
+
+def test_chirp_gain_factor_beyond_newton_range(hbl, orc):
+    """Particles whose gain factor 1 + chirp t leaves [0, 2] take the kernel's
+    division path (the Newton steps are sized for that range); both paths
+    against the oracle."""
+    n, chirp = 4001, 1e4
+    c = oracle_bunch(orc, n, 34)
+    c[2] = np.linspace(-1.05, 1.6, n) / chirp              # gain factor from -0.05 to 2.6
+    st = W.Stage(L=0.3, n0_m3=1e23, dE_MeV=9000.0, nsub=400, chirp=chirp)
+    z = to_dev(c)
+    ref = hbl.Ref.from_energy(1000.0)
+    hbl.apply_stage(z, st, ref, n=n)
+    g = to_host(z, n)
+    orc.push(c, [st], orc.Ref.from_energy(1000.0))
+    assert np.all(np.isfinite(g))
+    assert rel_err(g, c).max() < TOL
