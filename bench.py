@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--n", type=int, default=25_000_000)
     ap.add_argument("--epochs", type=int, default=1200, help="training epochs per surrogate")
     ap.add_argument("--pairs", type=int, default=1 << 20)
+    ap.add_argument("--lens-epochs", type=int, default=300, help="training epochs of the lens-chain surrogates")
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -338,6 +339,84 @@ def config_studies(log):
     return out
 
 
+def lens_optimisation_study(args, log):
+    """§4.4: the plasma lens of each interstage (position, focal length) is
+    optimised stage by stage for the horizontal emittance after the next
+    stage, with the stages taken by surrogates; the surrogate of the next
+    stage is trained just before each lens is optimised, on pairs pooled over
+    eight settings of that lens in the search box.  The lenses found are then
+    checked with the fine-step stages (full fidelity), against the starting
+    lenses."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+    from paper_2402_17248_amd.optimize import chain_emittances, optimise_lenses, train_stage_surrogate
+
+    # stage k + 1's surrogate is trained just before lens k is optimised, on pairs
+    # pooled over the start and seven seeded settings of lens k in the search box
+    # (the lenses before it fixed at the values found): the optimiser's inputs
+    box = ((2.0, 7.0), (1.6, 4.0))
+    rng = np.random.default_rng(7)
+    settings = [W.LENS_START] + [(float(p), float(f)) for p, f in
+                                 zip(rng.uniform(*box[0], 7), rng.uniform(*box[1], 7))]
+    wl_of = lambda lenses, n=1_000_000: W.c5_lens_chain(lenses, n=n)
+    t_train = 0.0
+    surs = [None] * 4
+
+    def train(k, lens_sets):
+        nonlocal t_train
+        t0 = time.perf_counter()
+        surs[k] = train_stage_surrogate(wl_of, k, lens_sets, 1 << 20, 300 + k, W.mlp_init_seed(k + 1),
+                                        W.shuffle_seed(k + 1), epochs=args.lens_epochs, log=log)
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t0
+
+    def before_interstage(k, lenses):
+        rest = [W.LENS_START] * (2 - k)
+        train(k + 1, [lenses[:k] + [s] + rest for s in settings])
+
+    train(0, [[W.LENS_START] * 3])
+    m = 1 << 17
+    wl = wl_of([W.LENS_START] * 3, m)
+    z0 = hbl.new_bunch(m)
+    hbl.fill_gaussian(z0, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=m)
+
+    def apply_sur(k, z, ref, pre, n):
+        surs[k].apply(z, ref, n=n, pre=pre)
+
+    stages = [hbl.element(seg) for seg in wl.beamline if not isinstance(seg, list)]
+
+    def apply_fine(k, z, ref, pre, n):
+        hbl.apply_stage(z, stages[k], ref, n=n, pre=pre)
+
+    t_train0 = t_train
+    t0 = time.perf_counter()
+    lenses, eps_opt, report = optimise_lenses(wl_of, W.LENS_START, z0, m, apply_sur,
+                                              bounds=box, max_evals=200, log=log,
+                                              before_interstage=before_interstage)
+    t_opt = time.perf_counter() - t0 - t_train + t_train0
+    evals = sum(r["evaluations"] for r in report)
+    N = 1_000_000
+    zf = hbl.new_bunch(N)
+    hbl.fill_gaussian(zf, 55, (0.0,) * 6, wl.bunch.sigma, n=N)
+    bg = [math.sqrt(((1000.0 + 10000.0 * (k + 1)) / hbl.MEC2_MEV) ** 2 - 1) for k in range(4)]
+    norm = lambda e: [v * b for v, b in zip(e, bg)]
+    fine_start = norm(chain_emittances(wl_of([W.LENS_START] * 3, N), zf, N, apply_fine))
+    fine_opt = norm(chain_emittances(wl_of(lenses, N), zf, N, apply_fine))
+    sur_opt = norm(chain_emittances(wl_of(lenses, N), zf, N, apply_sur))
+    log(f"lens optimisation: {evals} surrogate-chain evaluations in {t_opt:.2f} s "
+        f"({evals / t_opt:.0f}/s on {m} particles); normalised eps_x after stages 1-4, fine-step "
+        f"check: start {['%.3e' % v for v in fine_start]}, optimised {['%.3e' % v for v in fine_opt]} "
+        f"(surrogate chain {['%.3e' % v for v in sur_opt]})")
+    return {"lenses_start": [W.LENS_START] * 3, "lenses_found": lenses, "training_seconds": t_train,
+            "training_lens_settings": settings, "evaluations": evals, "optimisation_seconds": t_opt,
+            "evaluations_per_s": evals / t_opt, "sample_particles": m, "check_particles": N,
+            "eps_nx_fine_step_start": fine_start, "eps_nx_fine_step_optimised": fine_opt,
+            "eps_nx_surrogate_optimised": sur_opt, "per_interstage": report}
+
+
 def chain_equal_error(args, wl, chain, dt_sur, step_fn, log):
     """The staged chain at equal error: on the first 1e6 particles of the
     benchmark bunch, the emittance error of the surrogate chain and of the
@@ -496,10 +575,11 @@ def main():
         equal = chain_equal_error(args, wl, chain, dt_sur, time_chain, log)
         configs = config_studies(log)
 
-    single = single_chrom = None
+    single = single_chrom = lens_opt = None
     if not args.no_single_stage:
         single, _ = single_stage_study(args, log)
         single_chrom, _ = single_stage_study(args, log, chromatic=True)
+        lens_opt = lens_optimisation_study(args, log)
 
     # ---- dominant kernel: surrogate inference with the gaps fused (k_mlp_infer,
     # one launch per stage pass), timed inside the timed steps above
@@ -538,6 +618,7 @@ def main():
         "other_configs": configs,
         "single_stage_c4": single,
         "single_stage_c4_chromatic": single_chrom,
+        "lens_optimisation": lens_opt,
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
         "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,
                      "unit": "T VALU slots/s", "frac": alu_achieved / VALU_PEAK_TSLOTS,

@@ -112,6 +112,20 @@ def interstage() -> List[Element]:
              drift(0.5)] + chicane() + [drift(0.5)])
 
 
+# Plasma-lens interstage (§4.4: a plasma lens between stages whose position and
+# strength are optimised): D(p), thin lens f, D(LENS_GAP_DRIFT - p), the
+# four-dipole chicane (5 m), D 0.5 -- 13.3 m from one stage to the next, like
+# interstage().  Taking the chicane as a drift, point-to-point imaging with
+# magnification -1 puts the lens in the middle, p = 6.65 m, with f = 3.325 m.
+LENS_GAP_DRIFT = 7.8
+LENS_GAP_LENGTH = 13.3
+LENS_START = (5.0, 3.0)        # (position m, focal length m): where the optimisation starts
+
+
+def interstage_lens(p: float, f: float) -> List[Element]:
+    return [drift(p), lens(f), drift(LENS_GAP_DRIFT - p)] + chicane() + [drift(0.5)]
+
+
 def plasma_stage(dE_MeV=9000.0, nsub=2000) -> Stage:
     """0.3 m stage at n0 = 1e17 cm^-3 = 1e23 m^-3."""
     return Stage(L=0.3, n0_m3=1e23, dE_MeV=dE_MeV, nsub=nsub)
@@ -178,6 +192,20 @@ def c5_chain(n=25_000_000, seed=5, nsub=2000, n_stages=4) -> Workload:
         bl.append(interstage() if k < n_stages - 1 else triplet())
     return Workload("chain4_2.5e7", BunchSpec(n, seed), E0_MeV, bl,
                     "4 plasma stages (+10 GeV each) joined by imaging triplet+chicane interstages")
+
+
+def c5_lens_chain(lenses, n=25_000_000, seed=5, nsub=2000, widen=1.0) -> Workload:
+    """The four-stage chain with plasma-lens interstages; lenses = three
+    (position, focal length) pairs.  widen scales the transverse sigmas of the
+    initial bunch (wider training inputs)."""
+    bl: list = [triplet()]
+    for k in range(4):
+        bl.append(plasma_stage(10_000.0, nsub))
+        bl.append(interstage_lens(*lenses[k]) if k < 3 else triplet())
+    sig = BunchSpec(1, 1).sigma
+    sig = tuple(v * (widen if j in (0, 1, 3, 4) else 1.0) for j, v in enumerate(sig))
+    return Workload("chain4_lens", BunchSpec(n, seed, sigma=sig), E0_MeV, bl,
+                    "4 plasma stages joined by plasma-lens + chicane interstages")
 
 
 def c5_pair_seed(k: int) -> int:
