@@ -352,7 +352,8 @@ def lens_optimisation_study(args, log):
 
     import workloads as W
     from paper_2402_17248_amd import hbl
-    from paper_2402_17248_amd.optimize import chain_emittances, optimise_lenses, train_stage_surrogate
+    from paper_2402_17248_amd.optimize import (chain_emittances, chain_with_moment_lenses, optimise_lenses,
+                                                train_stage_surrogate)
 
     # stage k + 1's surrogate is trained just before lens k is optimised, on pairs
     # pooled over the start and seven seeded settings of lens k in the search box
@@ -406,15 +407,21 @@ def lens_optimisation_study(args, log):
     fine_start = norm(chain_emittances(wl_of([W.LENS_START] * 3, N), zf, N, apply_fine))
     fine_opt = norm(chain_emittances(wl_of(lenses, N), zf, N, apply_fine))
     sur_opt = norm(chain_emittances(wl_of(lenses, N), zf, N, apply_sur))
+    # the paper's reference strategy: centred lenses set from the moments after each stage
+    mom_lenses, mom_eps = chain_with_moment_lenses(lambda L: wl_of(L, N), zf, N, apply_fine,
+                                                   W.LENS_GAP_LENGTH / 2)
+    fine_mom = norm(mom_eps)
     log(f"lens optimisation: {evals} surrogate-chain evaluations in {t_opt:.2f} s "
         f"({evals / t_opt:.0f}/s on {m} particles); normalised eps_x after stages 1-4, fine-step "
         f"check: start {['%.3e' % v for v in fine_start]}, optimised {['%.3e' % v for v in fine_opt]} "
-        f"(surrogate chain {['%.3e' % v for v in sur_opt]})")
+        f"(surrogate chain {['%.3e' % v for v in sur_opt]}); moment-driven centred lenses "
+        f"{['%.3e' % v for v in fine_mom]}")
     return {"lenses_start": [W.LENS_START] * 3, "lenses_found": lenses, "training_seconds": t_train,
             "training_lens_settings": settings, "evaluations": evals, "optimisation_seconds": t_opt,
             "evaluations_per_s": evals / t_opt, "sample_particles": m, "check_particles": N,
             "eps_nx_fine_step_start": fine_start, "eps_nx_fine_step_optimised": fine_opt,
-            "eps_nx_surrogate_optimised": sur_opt, "per_interstage": report}
+            "eps_nx_surrogate_optimised": sur_opt, "per_interstage": report,
+            "moment_driven_lenses": mom_lenses, "eps_nx_fine_step_moment_driven": fine_mom}
 
 
 def chain_equal_error(args, wl, chain, dt_sur, step_fn, log):

@@ -35,3 +35,35 @@ def test_sequential_lens_optimisation_finds_imaging(orc):
         orc.push(M, W.interstage_lens(p, f), orc.Ref.from_energy(11_000.0))
         assert abs(M[0, 3]) < 0.02                         # start: R12 = -0.53 m
     assert all(r["evaluations"] <= 150 + 4 for r in report)    # scipy may finish its last step
+
+
+def test_moment_driven_lenses_preserve_emittance(orc):
+    """Lenses set from the beam moments measured after each stage (centred,
+    waist at the next entrance): the next stage sees a beam at a waist, and
+    the emittance after stage 1 is kept through the chain (fine-step stages)."""
+    from paper_2402_17248_amd import hbl
+    from paper_2402_17248_amd.optimize import chain_emittances, chain_with_moment_lenses, twiss_from_moments
+    n, nsub = 20_000, 300
+    wl_of = lambda lenses: W.c5_lens_chain(lenses, n=n, nsub=nsub)
+    wl = wl_of([W.LENS_START] * 3)
+    z0 = hbl.new_bunch(n)
+    hbl.fill_gaussian(z0, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+    stages = [hbl.element(s) for s in wl.beamline if not isinstance(s, list)]
+
+    def apply(k, z, ref, pre, m):
+        hbl.apply_stage(z, stages[k], ref, n=m, pre=pre)
+
+    lenses, eps = chain_with_moment_lenses(wl_of, z0, n, apply, W.LENS_GAP_LENGTH / 2)
+    assert chain_emittances(wl_of(lenses), z0, n, apply)[-1] == eps[-1]
+    assert max(eps) < 1.2 * eps[0]
+    # the beam entering each later stage is at a waist: |alpha| small
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    z = z0.clone()
+    for k in range(3):
+        apply(k, z, ref, hbl.Lattice(wl_of(lenses).beamline[2 * k], ref), n)
+        w = z.clone()
+        r = ref.copy()
+        hbl.Lattice(wl_of(lenses).beamline[2 + 2 * k], r).push(w, r, n=n)
+        _, cov = hbl.moments(w, n=n)
+        _, alpha, _ = twiss_from_moments(cov)
+        assert abs(alpha) < 1e-3, (k, alpha)
