@@ -706,3 +706,167 @@ int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
     free(tidx); free(perm); free(g); free(v); free(m);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* PReLU network, the shape the paper trains (§3 Eq. 2 and 3; §4.2: several
+ * hidden layers of equal width).  Hidden layer l < H:
+ *   v = A_l h_l + b_l,   h_{l+1} = prelu(v) = v if v > 0, a_l v otherwise,
+ * with ONE learned slope a_l per hidden layer; output A_H h_H + b_H.  Flat
+ * parameters: A_0 (out x in, row-major), b_0, a_0, A_1, b_1, a_1, ...,
+ * A_{H-1}, b_{H-1}, a_{H-1}, A_H, b_H.  Weights and biases draw like the
+ * tanh network's (parameter p: Philox block (p, 0, 0, 'MLPI')); slopes start
+ * at 0.25 and draw nothing.
+ * Mode 1 applies the GPU rounding points: network input FP32; first layer
+ * FP32 weights, pre-activation rounded to FP32; other layers bf16 weights
+ * and bf16 activations with the pre-activation rounded to FP32; the slope
+ * product in FP32; each hidden activation rounded to bf16; output FP32.    */
+/* ------------------------------------------------------------------ */
+static int64_t prelu_layer_offset(const orc_shape* sh, int l)
+{
+    int64_t off = 0;
+    for (int q = 0; q < l; q++) off += (int64_t)layer_out(sh, q) * (layer_in(sh, q) + 1) + 1;
+    return off;
+}
+
+int64_t orc_prelu_nparams(const orc_shape* sh)
+{
+    return prelu_layer_offset(sh, sh->hidden) + (int64_t)sh->n_out * (sh->width + 1);
+}
+
+int orc_prelu_init(const orc_shape* sh, uint64_t seed, float* params)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int l = 0; l <= sh->hidden; l++) {
+        const int64_t off = prelu_layer_offset(sh, l);
+        const int64_t cnt = (int64_t)layer_out(sh, l) * (layer_in(sh, l) + 1);
+        const double bound = 1.0 / sqrt((double)layer_in(sh, l));
+        for (int64_t q = 0; q < cnt; q++) {
+            const int64_t p = off + q;
+            uint32_t ctr[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), 0u, 0x4D4C5049u};
+            uint32_t o[4];
+            orc_philox4x32_10(ctr, key, o);
+            const double u = (double)(o[0] >> 8) * (1.0 / 16777216.0);
+            params[p] = (float)((2.0 * u - 1.0) * bound);
+        }
+        if (l < sh->hidden) params[off + cnt] = 0.25f;
+    }
+    return 0;
+}
+
+/* pre[l][o]: pre-activation of hidden layer l (as used by the slope). */
+typedef struct { double act[8][MAXW]; double pre[8][MAXW]; double yhat[MAXW]; } prelu_state;
+
+static void prelu_forward_one(const orc_shape* sh, const float* prm, const double* norm, int mode,
+                              const double* xin, prelu_state* st)
+{
+    const int H = sh->hidden;
+    for (int j = 0; j < sh->n_in; j++) {
+        const double xh = (xin[j] - norm[j]) / norm[6 + j];
+        st->act[0][j] = mode ? (double)(float)xh : xh;
+    }
+    for (int l = 0; l <= H; l++) {
+        const int ni = layer_in(sh, l), no = layer_out(sh, l);
+        const float* A = prm + prelu_layer_offset(sh, l);
+        const float* b = A + (int64_t)no * ni;
+        const float slope = (l < H) ? b[no] : 0.0f;
+        const double* in = st->act[l];
+        for (int o = 0; o < no; o++) {
+            double acc = (double)b[o];
+            for (int i = 0; i < ni; i++) {
+                const float w = A[(int64_t)o * ni + i];
+                acc += (double)((mode && l > 0) ? orc_bf16(w) : w) * in[i];
+            }
+            if (l == H) {
+                st->yhat[o] = mode ? (double)(float)acc : acc;
+                continue;
+            }
+            double v;
+            if (mode) {
+                const float v32 = (float)acc;
+                v = (double)orc_bf16(v32 > 0.0f ? v32 : slope * v32);
+                st->pre[l][o] = (double)v32;
+            } else {
+                v = acc > 0.0 ? acc : (double)slope * acc;
+                st->pre[l][o] = acc;
+            }
+            st->act[l + 1][o] = v;
+        }
+    }
+}
+
+int orc_prelu_apply(const orc_shape* sh, const float* params, const double* norm, int mode,
+                    const double* zin, double* zout, int64_t n, int64_t ld)
+{
+    if (sh->width > MAXW || sh->hidden < 1 || sh->hidden > 7 || sh->n_in != 6 || sh->n_out != 6) return -1;
+    prelu_state* st = (prelu_state*)malloc(sizeof(prelu_state));
+    for (int64_t i = 0; i < n; i++) {
+        double x[6];
+        for (int j = 0; j < 6; j++) x[j] = ROW(zin, j, ld)[i];
+        prelu_forward_one(sh, params, norm, mode, x, st);
+        for (int j = 0; j < 6; j++) ROW(zout, j, ld)[i] = norm[12 + j] + norm[18 + j] * st->yhat[j];
+    }
+    free(st);
+    return 0;
+}
+
+/* MSE (Eq. 4) over b pairs x 6 outputs in normalised coordinates and its
+ * exact FP64 gradient by reverse-mode differentiation (mode 0 only).  The
+ * slope gradient collects the error times the pre-activation wherever the
+ * pre-activation is not positive. */
+int orc_prelu_loss_grad(const orc_shape* sh, const float* params, const double* norm,
+                        const double* zin, const double* zout, int64_t ld,
+                        const int64_t* idx, int64_t b, double* grad, double* loss)
+{
+    if (sh->width > MAXW || sh->hidden < 1 || sh->hidden > 7 || b <= 0) return -1;
+    const int H = sh->hidden;
+    const int64_t np = orc_prelu_nparams(sh);
+    memset(grad, 0, np * sizeof(double));
+    prelu_state* st = (prelu_state*)malloc(sizeof(prelu_state));
+    double* dl = (double*)malloc(MAXW * sizeof(double));
+    double* dprev = (double*)malloc(MAXW * sizeof(double));
+    double lsum = 0.0;
+    const double scale = 2.0 / ((double)b * sh->n_out);
+    for (int64_t q = 0; q < b; q++) {
+        const int64_t i = idx[q];
+        double x[6];
+        for (int j = 0; j < 6; j++) x[j] = ROW(zin, j, ld)[i];
+        prelu_forward_one(sh, params, norm, 0, x, st);
+        for (int o = 0; o < sh->n_out; o++) {
+            const double d = st->yhat[o] - (ROW(zout, o, ld)[i] - norm[12 + o]) / norm[18 + o];
+            dl[o] = d * scale;              /* dL/d(output) */
+            lsum += d * d;
+        }
+        for (int l = H; l >= 0; l--) {
+            const int ni = layer_in(sh, l), no = layer_out(sh, l);
+            const float* A = params + prelu_layer_offset(sh, l);
+            double* gA = grad + prelu_layer_offset(sh, l);
+            double* gb = gA + (int64_t)no * ni;
+            const double* in = st->act[l];
+            /* dl holds dL/dv for this layer's pre-activations v */
+            for (int o = 0; o < no; o++) {
+                for (int ii = 0; ii < ni; ii++) gA[(int64_t)o * ni + ii] += dl[o] * in[ii];
+                gb[o] += dl[o];
+            }
+            if (l == 0) break;
+            /* back through layer l-1's PReLU: h = prelu(u), u = pre[l-1] */
+            const float* Ap = params + prelu_layer_offset(sh, l - 1);
+            const double slope = (double)Ap[(int64_t)ni * (layer_in(sh, l - 1) + 1)];
+            double* gslope = grad + prelu_layer_offset(sh, l - 1) + (int64_t)ni * (layer_in(sh, l - 1) + 1);
+            for (int ii = 0; ii < ni; ii++) {
+                double e = 0.0;
+                for (int o = 0; o < no; o++) e += (double)A[(int64_t)o * ni + ii] * dl[o];
+                const double u = st->pre[l - 1][ii];
+                if (u > 0.0) {
+                    dprev[ii] = e;
+                } else {
+                    dprev[ii] = slope * e;
+                    *gslope += e * u;
+                }
+            }
+            memcpy(dl, dprev, ni * sizeof(double));
+        }
+    }
+    *loss = lsum / ((double)b * sh->n_out);
+    free(dprev); free(dl); free(st);
+    return 0;
+}

@@ -83,6 +83,18 @@ int orc_adam_step(int64_t np, float* params, double* m, double* v, const double*
 int orc_norm_stats(const double* zin, const double* zout, int64_t n_train, int64_t ld, double* norm);
 /* Epoch permutation (Fisher-Yates driven by Philox). */
 int orc_epoch_perm(int64_t n, uint64_t seed, int64_t epoch, int64_t* perm);
+/* PReLU network of the paper's shape (Eq. 2 and 3): one learned slope per
+ * hidden layer; flat layout A_0, b_0, a_0, ..., A_{H-1}, b_{H-1}, a_{H-1},
+ * A_H, b_H; slopes start at 0.25.  Mode 0 = FP64, mode 1 = the GPU rounding
+ * points (FP32 first layer, bf16 weights and activations elsewhere). */
+int64_t orc_prelu_nparams(const orc_shape* sh);
+int orc_prelu_init(const orc_shape* sh, uint64_t seed, float* params);
+int orc_prelu_apply(const orc_shape* sh, const float* params, const double* norm, int mode,
+                    const double* zin, double* zout, int64_t n, int64_t ld);
+/* Loss (Eq. 4) and exact FP64 gradient over the pairs idx[0..b). */
+int orc_prelu_loss_grad(const orc_shape* sh, const float* params, const double* norm,
+                        const double* zin, const double* zout, int64_t ld,
+                        const int64_t* idx, int64_t b, double* grad, double* loss);
 /* Full training loop; loss_log[2*e] = mean train loss, [2*e+1] = test loss. */
 int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
                   const double* zin, const double* zout, int64_t n_pairs, int64_t ld,

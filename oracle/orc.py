@@ -64,6 +64,12 @@ def lib():
         L.orc_bf16.argtypes = [C.c_float]
         L.orc_bf16.restype = C.c_float
         fp = C.POINTER(C.c_float)
+        L.orc_prelu_nparams.argtypes = [C.POINTER(_Shape)]
+        L.orc_prelu_nparams.restype = i64
+        L.orc_prelu_init.argtypes = [C.POINTER(_Shape), C.c_uint64, fp]
+        L.orc_prelu_apply.argtypes = [C.POINTER(_Shape), fp, dp, C.c_int, dp, dp, i64, i64]
+        L.orc_prelu_loss_grad.argtypes = [C.POINTER(_Shape), fp, dp, dp, dp, i64,
+                                          C.POINTER(C.c_int64), i64, dp, dp]
         L.orc_mlp_nparams.argtypes = [C.POINTER(_Shape)]
         L.orc_mlp_nparams.restype = i64
         L.orc_mlp_init.argtypes = [C.POINTER(_Shape), C.c_uint64, fp]
@@ -271,3 +277,37 @@ def mlp_train(sh, params, zin, zout, batch, epochs, lr=1e-3, b1=0.9, b2=0.999, e
                                lr if lr_final is None else lr_final, b1, b2, eps,
                                train_frac, shuffle_seed, _dp(log)), "train")
     return params, norm, log.reshape(epochs, 2)
+
+
+# ---------------------------------------------------------------- PReLU network
+def prelu_nparams(sh):
+    return int(lib().orc_prelu_nparams(C.byref(sh)))
+
+
+def prelu_init(sh, seed):
+    p = np.empty(prelu_nparams(sh), dtype=np.float32)
+    lib().orc_prelu_init(C.byref(sh), seed, _fp(p))
+    return p
+
+
+def prelu_apply(sh, params, norm, zin, mode=0):
+    zin = _bunch(zin)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    norm = np.ascontiguousarray(norm, dtype=np.float64)
+    out = np.empty_like(zin)
+    _check(lib().orc_prelu_apply(C.byref(sh), _fp(params), _dp(norm), mode, _dp(zin), _dp(out),
+                                 zin.shape[1], zin.shape[1]), "prelu_apply")
+    return out
+
+
+def prelu_loss_grad(sh, params, norm, zin, zout, idx):
+    zin, zout = _bunch(zin), _bunch(zout)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    norm = np.ascontiguousarray(norm, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    g = np.empty(prelu_nparams(sh))
+    loss = C.c_double()
+    _check(lib().orc_prelu_loss_grad(C.byref(sh), _fp(params), _dp(norm), _dp(zin), _dp(zout),
+                                     zin.shape[1], idx.ctypes.data_as(C.POINTER(C.c_int64)), len(idx),
+                                     _dp(g), C.byref(loss)), "prelu_loss_grad")
+    return loss.value, g
