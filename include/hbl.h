@@ -273,6 +273,53 @@ hbl_status hbl_surrogate_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_
 hbl_status hbl_surrogate_save(const hbl_surrogate* m, const char* path);
 hbl_status hbl_surrogate_load(const char* path, hbl_surrogate** out);
 
+/* ------------------------------------------------------ wide PReLU surrogate */
+
+/* The network shape the paper trains for its stages (§3 Eq. 2 and 3; §4.2:
+ * three hidden layers of 700 for most stages, five of 900 for the first
+ * ones): shape {6, W, H, 6} with 8 <= W <= 1024 and 1 <= H <= 7, hidden
+ * layers h_{l+1} = PReLU_{a_l}(A_l h_l + b_l), PReLU_a(v) = v for v > 0 and
+ * a v otherwise, one learned slope a_l per hidden layer; output A_H h_H + b_H;
+ * the same per-direction normalisation as the tanh surrogate.  FP32 master
+ * parameters, flat layout A_0 (W x 6, row-major [out][in]), b_0, a_0, A_1
+ * (W x W), b_1, a_1, ..., A_{H-1}, b_{H-1}, a_{H-1}, A_H (6 x W), b_H:
+ * 6W + W + 1 + (H - 1)(W^2 + W + 1) + 6W + 6 floats.
+ * Arithmetic: the first layer in FP32 on the vector ALU (FP32 network input);
+ * the W x W layers and the output layer as bf16 products with FP32
+ * accumulation on the matrix cores, bias and PReLU in FP32, each hidden
+ * activation rounded to bf16; output FP32, de-normalised in FP64.
+ * Device memory held by a network: its parameters, their bf16 image and two
+ * activation buffers of 65536 x W' bf16 (W' = W rounded up to 64; 2 x 126 MB
+ * at W = 900), allocated at creation.  Calls that use one network must be
+ * ordered (one stream, or synchronised): they share those buffers. */
+typedef struct hbl_prelu_net hbl_prelu_net;
+
+/* Weights and biases U(-1/sqrt(fan_in), 1/sqrt(fan_in)), parameter p (flat
+ * index) from word 0 of Philox4x32-10 block (p, 0, 0, 'MLPI') keyed by
+ * init_seed, u = (word >> 8) 2^-24, value (2u - 1)/sqrt(fan_in); slopes 0.25.
+ * Synchronous.  HBL_EINVAL for a shape outside the limits above. */
+hbl_status hbl_prelu_create(const hbl_mlp_shape* shape, uint64_t init_seed, hbl_prelu_net** out);
+hbl_status hbl_prelu_destroy(hbl_prelu_net* m);
+hbl_status hbl_prelu_num_params(const hbl_prelu_net* m, int64_t* n);
+/* SYNC.  Copy the FP32 parameters to / from host memory (n floats, finite). */
+hbl_status hbl_prelu_get_params(const hbl_prelu_net* m, float* host, int64_t n);
+hbl_status hbl_prelu_set_params(hbl_prelu_net* m, const float* host, int64_t n);
+/* norm24 as for hbl_surrogate_set_norm (host FP64, sd > 0). */
+hbl_status hbl_prelu_set_norm(hbl_prelu_net* m, const double norm24[24]);
+hbl_status hbl_prelu_get_norm(const hbl_prelu_net* m, double norm24[24]);
+/* Declare the stage the network replaces (as hbl_surrogate_set_stage). */
+hbl_status hbl_prelu_set_stage(hbl_prelu_net* m, const hbl_element* stage, const hbl_ref* at_entry);
+/* ASYNC.  Inference in place on n particles of the DEVICE bunch z (§4.3),
+ * in chunks of 65536 particles; advances ref like the declared stage. */
+hbl_status hbl_prelu_apply(double* z, int64_t n, int64_t ld, const hbl_prelu_net* m, hbl_ref* ref,
+                           hbl_stream stream);
+/* ASYNC.  pre lattice, the network, post lattice in the same launches (pre
+ * applied where the network input is formed, post where its output is
+ * written); needs a declared stage; lattices as for hbl_surrogate_apply_gaps. */
+hbl_status hbl_prelu_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
+                                const hbl_prelu_net* m, const hbl_lattice* post, hbl_ref* ref,
+                                hbl_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1231,3 +1231,241 @@ hbl_status hbl_surrogate_load(const char* path, hbl_surrogate** out) {
 }
 
 }  // extern "C"
+
+// ====================================================== wide PReLU surrogate
+struct hbl_prelu_net {
+    int device;
+    hbl_mlp_shape shape;
+    int64_t nparams;
+    int64_t chunk;            // particles per inference chunk (multiple of the tile)
+    float* d_params;          // FP32 master parameters
+    char* d_image;            // one allocation: the DenseImage arrays
+    uint16_t* d_buf[2];       // activation ping-pong buffers, chunk x wp bf16 each
+    DenseImage im;
+    double norm[24];
+    bool has_norm;
+    bool has_stage;
+    double dE_MeV, L, gamma_in;
+};
+
+namespace {
+
+constexpr int64_t kPreluChunk = 65536;
+
+int64_t prelu_nparams_of(const hbl_mlp_shape* sh) {
+    const int64_t W = sh->width, H = sh->hidden;
+    return 6 * W + W + 1 + (H - 1) * (W * W + W + 1) + 6 * W + 6;
+}
+
+hbl_status check_prelu_shape(const hbl_mlp_shape* sh) {
+    HBL_REQUIRE(sh, "prelu: NULL shape");
+    HBL_REQUIRE(sh->n_in == 6 && sh->n_out == 6, "prelu: n_in and n_out must be 6");
+    HBL_REQUIRE(sh->width >= 8 && sh->width <= 64 * kDenseMaxMT, "prelu: width %d outside [8, %d]", sh->width,
+                64 * kDenseMaxMT);
+    HBL_REQUIRE(sh->hidden >= 1 && sh->hidden <= kDenseMaxHidden, "prelu: hidden %d outside [1, %d]", sh->hidden,
+                kDenseMaxHidden);
+    return HBL_OK;
+}
+
+void prelu_free(hbl_prelu_net* m) {
+    if (!m) return;
+    void* ptrs[] = {m->d_params, m->d_image, m->d_buf[0], m->d_buf[1]};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+// Lay the DenseImage arrays out in one allocation (256-byte aligned pieces).
+size_t prelu_image_layout(const hbl_mlp_shape* sh, DenseImage* im, char* base) {
+    const int64_t wp = (sh->width + 63) / 64 * 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    im->wp = (int32_t)wp;
+    im->w0 = (float*)take(sizeof(float) * wp * 6);
+    im->b0 = (float*)take(sizeof(float) * wp);
+    im->slope = (float*)take(sizeof(float) * kDenseMaxHidden);
+    for (int l = 0; l <= kDenseMaxHidden; ++l) { im->w[l] = nullptr; im->b[l] = nullptr; }
+    for (int l = 1; l <= sh->hidden; ++l) {
+        const int64_t rows = l == sh->hidden ? 16 : wp;
+        im->w[l] = (uint16_t*)take(sizeof(uint16_t) * rows * wp);
+        im->b[l] = (float*)take(sizeof(float) * rows);
+    }
+    return off;
+}
+
+hbl_status prelu_repack(hbl_prelu_net* m, hipStream_t s) {
+    const DenseShape sh{m->shape.width, m->shape.hidden};
+    HBL_HIP(launch_dense_pack(m->d_params, sh, m->im, s));
+    return HBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_prelu_create(const hbl_mlp_shape* shape, uint64_t init_seed, hbl_prelu_net** out) {
+    clear_error();
+    HBL_REQUIRE(out, "prelu_create: NULL output handle");
+    *out = nullptr;
+    if (hbl_status st = check_prelu_shape(shape)) return st;
+    const int64_t np = prelu_nparams_of(shape);
+    std::vector<float> p(np);
+    const int W = shape->width, H = shape->hidden;
+    int64_t off = 0;
+    for (int l = 0; l <= H; ++l) {
+        const int ni = l == 0 ? 6 : W, no = l == H ? 6 : W;
+        const double bound = 1.0 / sqrt((double)ni);
+        const int64_t cnt = (int64_t)no * (ni + 1);
+        for (int64_t q = 0; q < cnt; ++q, ++off) {
+            uint32_t c[4] = {(uint32_t)off, (uint32_t)((uint64_t)off >> 32), 0u, 0x4D4C5049u};
+            philox_host(c, (uint32_t)init_seed, (uint32_t)(init_seed >> 32));
+            const double u = (double)(c[0] >> 8) * (1.0 / 16777216.0);
+            p[off] = (float)((2.0 * u - 1.0) * bound);
+        }
+        if (l < H) p[off++] = 0.25f;
+    }
+    hbl_prelu_net* m = new (std::nothrow) hbl_prelu_net();
+    if (!m) { set_error(HBL_ENOMEM, "prelu_create: out of host memory"); return HBL_ENOMEM; }
+    m->shape = *shape;
+    m->nparams = np;
+    if (hipGetDevice(&m->device) != hipSuccess) { delete m; set_error(HBL_EHIP, "prelu_create: no HIP device"); return HBL_EHIP; }
+    const size_t img_bytes = prelu_image_layout(shape, &m->im, nullptr);
+    m->chunk = kPreluChunk;
+    const size_t buf_bytes = sizeof(uint16_t) * (size_t)m->chunk * m->im.wp;
+    hipError_t e = hipMalloc((void**)&m->d_params, sizeof(float) * np);
+    if (e == hipSuccess) e = hipMalloc((void**)&m->d_image, img_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&m->d_buf[0], buf_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&m->d_buf[1], buf_bytes);
+    if (e != hipSuccess) { prelu_free(m); set_error(HBL_ENOMEM, "prelu_create: device allocation failed"); return HBL_ENOMEM; }
+    prelu_image_layout(shape, &m->im, m->d_image);
+    e = hipMemset(m->d_image, 0, img_bytes);
+    if (e == hipSuccess) e = hipMemcpy(m->d_params, p.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_dense_pack(m->d_params, DenseShape{W, H}, m->im, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { prelu_free(m); set_error(HBL_EHIP, "prelu_create: %s", hipGetErrorString(e)); return HBL_EHIP; }
+    *out = m;
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_destroy(hbl_prelu_net* m) {
+    clear_error();
+    if (m) (void)hipDeviceSynchronize();
+    prelu_free(m);
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_num_params(const hbl_prelu_net* m, int64_t* n) {
+    clear_error();
+    HBL_REQUIRE(m && n, "prelu_num_params: NULL argument");
+    *n = m->nparams;
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_get_params(const hbl_prelu_net* m, float* host, int64_t n) {
+    clear_error();
+    HBL_REQUIRE(m && host, "prelu_get_params: NULL argument");
+    HBL_REQUIRE(n == m->nparams, "prelu_get_params: n = %lld, the network has %lld", (long long)n, (long long)m->nparams);
+    HBL_HIP(hipDeviceSynchronize());
+    HBL_HIP(hipMemcpy(host, m->d_params, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_set_params(hbl_prelu_net* m, const float* host, int64_t n) {
+    clear_error();
+    HBL_REQUIRE(m && host, "prelu_set_params: NULL argument");
+    HBL_REQUIRE(n == m->nparams, "prelu_set_params: n = %lld, the network has %lld", (long long)n, (long long)m->nparams);
+    for (int64_t q = 0; q < n; ++q) HBL_REQUIRE(isfinite(host[q]), "prelu_set_params: parameter %lld not finite", (long long)q);
+    HBL_HIP(hipDeviceSynchronize());
+    HBL_HIP(hipMemcpy(m->d_params, host, sizeof(float) * n, hipMemcpyHostToDevice));
+    if (hbl_status st = prelu_repack(m, nullptr)) return st;
+    HBL_HIP(hipDeviceSynchronize());
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_set_norm(hbl_prelu_net* m, const double norm24[24]) {
+    clear_error();
+    HBL_REQUIRE(m && norm24, "prelu_set_norm: NULL argument");
+    if (hbl_status st = check_norm(norm24)) return st;
+    memcpy(m->norm, norm24, sizeof m->norm);
+    m->has_norm = true;
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_get_norm(const hbl_prelu_net* m, double norm24[24]) {
+    clear_error();
+    HBL_REQUIRE(m && norm24, "prelu_get_norm: NULL argument");
+    if (!m->has_norm) { set_error(HBL_ESTATE, "prelu_get_norm: no normalisation set"); return HBL_ESTATE; }
+    memcpy(norm24, m->norm, sizeof m->norm);
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_set_stage(hbl_prelu_net* m, const hbl_element* stage, const hbl_ref* at_entry) {
+    clear_error();
+    HBL_REQUIRE(m && stage, "prelu_set_stage: NULL argument");
+    HBL_REQUIRE(stage->kind == HBL_STAGE, "prelu_set_stage: element is not a stage");
+    HBL_REQUIRE(finite_pos(stage->L) && isfinite(stage->dE_MeV), "prelu_set_stage: bad L or dE");
+    if (hbl_status st = check_ref(at_entry)) return st;
+    HBL_REQUIRE(at_entry->gamma + stage->dE_MeV / at_entry->mass_MeV > 1.0, "prelu_set_stage: exit gamma must exceed 1");
+    m->has_stage = true;
+    m->dE_MeV = stage->dE_MeV;
+    m->L = stage->L;
+    m->gamma_in = at_entry->gamma;
+    return HBL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hbl_status prelu_apply_impl(double* z, int64_t n, int64_t ld, const hbl_lattice* pre, const hbl_prelu_net* m,
+                            const hbl_lattice* post, hbl_ref* ref, hbl_stream stream) {
+    clear_error();
+    if (hbl_status st = check_bunch(z, n, ld, "prelu_apply")) return st;
+    HBL_REQUIRE(m, "prelu_apply: NULL network");
+    if (!m->has_norm) { set_error(HBL_ESTATE, "prelu_apply: no normalisation set"); return HBL_ESTATE; }
+    HBL_REQUIRE(!(pre || post) || m->has_stage, "prelu_apply: gap lattices need a declared stage");
+    if (m->has_stage) {
+        if (hbl_status st = check_ref(ref)) return st;
+        HBL_REQUIRE(fabs(ref->gamma / m->gamma_in - 1.0) < 1e-12,
+                    "prelu_apply: reference gamma %.17g differs from the declared entry gamma %.17g", ref->gamma,
+                    m->gamma_in);
+        if (hbl_status st = check_gap(pre, ref->gamma, "prelu_apply: entrance")) return st;
+        if (hbl_status st = check_gap(post, ref->gamma + m->dE_MeV / ref->mass_MeV, "prelu_apply: exit")) return st;
+    }
+    if (n > 0) {
+        DenseNorm nm;
+        for (int j = 0; j < 6; ++j) {
+            nm.mu_in[j] = m->norm[j];
+            nm.sd_in[j] = m->norm[6 + j];
+            nm.mu_out[j] = m->norm[12 + j];
+            nm.sd_out[j] = m->norm[18 + j];
+        }
+        HBL_HIP(launch_dense_infer(z, n, ld, DenseShape{m->shape.width, m->shape.hidden}, m->im, nm, view_of(pre),
+                                   view_of(post), m->d_buf[0], m->d_buf[1], m->chunk, (hipStream_t)stream));
+    }
+    if (m->has_stage) {
+        ref->gamma += m->dE_MeV / ref->mass_MeV;
+        ref->s += (pre ? pre->length : 0.0) + m->L + (post ? post->length : 0.0);
+    }
+    return HBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_prelu_apply(double* z, int64_t n, int64_t ld, const hbl_prelu_net* m, hbl_ref* ref,
+                           hbl_stream stream) {
+    return prelu_apply_impl(z, n, ld, nullptr, m, nullptr, ref, stream);
+}
+
+hbl_status hbl_prelu_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre, const hbl_prelu_net* m,
+                                const hbl_lattice* post, hbl_ref* ref, hbl_stream stream) {
+    return prelu_apply_impl(z, n, ld, pre, m, post, ref, stream);
+}
+
+}  // extern "C"

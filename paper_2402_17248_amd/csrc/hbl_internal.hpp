@@ -111,6 +111,32 @@ hipError_t launch_eval_loss(const double* zin, const double* zout, int64_t ld, i
                             const uint32_t* img, const double* norm24, double* part, double* out,
                             hipStream_t s);
 
+// Wide PReLU surrogate (hidden width W <= 1024, 1..7 hidden layers).
+constexpr int kDenseMaxMT = 16;          // Wp / 64 for Wp <= 1024
+constexpr int kDenseMaxHidden = 7;
+struct DenseShape {
+    int32_t width, hidden;
+};
+// Device image of the network, rebuilt from the FP32 master parameters.
+struct DenseImage {
+    int32_t wp;                          // width rounded up to 64
+    float* w0;                           // [wp][6] first layer, FP32
+    float* b0;                           // [wp]
+    float* slope;                        // [hidden] PReLU slopes
+    uint16_t* w[kDenseMaxHidden + 1];    // layer l >= 1: bf16 [wp][wp] (output layer [16][wp])
+    float* b[kDenseMaxHidden + 1];       // layer l >= 1: [wp] (output layer [16])
+};
+struct DenseNorm {
+    double mu_in[6], sd_in[6], mu_out[6], sd_out[6];
+};
+int dense_tile_rows();
+hipError_t launch_dense_pack(const float* params, const DenseShape& sh, const DenseImage& im, hipStream_t s);
+// Inference over n particles in chunks of `chunk` (a multiple of
+// dense_tile_rows()); buf0/buf1: chunk x wp bf16 each.
+hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape& sh, const DenseImage& im,
+                              const DenseNorm& nm, const LatticeView& pre, const LatticeView& post,
+                              uint16_t* buf0, uint16_t* buf1, int64_t chunk, hipStream_t s);
+
 // Per-device library workspace (grow-only, freed at exit).
 double* workspace(size_t bytes);
 

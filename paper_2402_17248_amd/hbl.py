@@ -96,6 +96,16 @@ def _load():
         "hbl_surrogate_apply_gaps": ([vp, i64, i64, vp, vp, vp, C.POINTER(Ref), vp], st),
         "hbl_surrogate_save": ([vp, C.c_char_p], st),
         "hbl_surrogate_load": ([C.c_char_p, C.POINTER(vp)], st),
+        "hbl_prelu_create": ([C.POINTER(MlpShape), C.c_uint64, C.POINTER(vp)], st),
+        "hbl_prelu_destroy": ([vp], st),
+        "hbl_prelu_num_params": ([vp, C.POINTER(i64)], st),
+        "hbl_prelu_get_params": ([vp, C.POINTER(C.c_float), i64], st),
+        "hbl_prelu_set_params": ([vp, C.POINTER(C.c_float), i64], st),
+        "hbl_prelu_get_norm": ([vp, dp], st),
+        "hbl_prelu_set_norm": ([vp, dp], st),
+        "hbl_prelu_set_stage": ([vp, C.POINTER(Element), C.POINTER(Ref)], st),
+        "hbl_prelu_apply": ([vp, i64, i64, vp, C.POINTER(Ref), vp], st),
+        "hbl_prelu_apply_gaps": ([vp, i64, i64, vp, vp, vp, C.POINTER(Ref), vp], st),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -323,6 +333,70 @@ class Surrogate:
     def close(self):
         if getattr(self, "_h", None):
             lib.hbl_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PreluNet:
+    """The paper-shaped stage surrogate owned by libhbl: H hidden layers of
+    width W with PReLU (one learned slope each), e.g. 3 x 700 or 5 x 900."""
+
+    def __init__(self, width: int, hidden: int, seed: int = 0):
+        h = C.c_void_p()
+        _call("hbl_prelu_create", C.byref(MlpShape(6, width, hidden, 6)), seed, C.byref(h))
+        self._h = h
+        self.width, self.hidden = width, hidden
+        n = C.c_int64()
+        _call("hbl_prelu_num_params", self._h, C.byref(n))
+        self.n_params = n.value
+
+    def flops_per_particle(self) -> int:
+        """Multiply-adds x 2 of one forward pass (the network as defined, unpadded)."""
+        W, H = self.width, self.hidden
+        return 2 * (6 * W + (H - 1) * W * W + 6 * W)
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        _call("hbl_prelu_get_params", self._h, out.ctypes.data_as(C.POINTER(C.c_float)), self.n_params)
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _call("hbl_prelu_set_params", self._h, p.ctypes.data_as(C.POINTER(C.c_float)), len(p))
+
+    def get_norm(self):
+        out = (C.c_double * 24)()
+        _call("hbl_prelu_get_norm", self._h, out)
+        return list(out)
+
+    def set_norm(self, norm):
+        _call("hbl_prelu_set_norm", self._h, (C.c_double * 24)(*norm))
+
+    def set_stage(self, stage, ref_at_entry: Ref):
+        el = stage if isinstance(stage, Element) else element(stage)
+        _call("hbl_prelu_set_stage", self._h, C.byref(el), C.byref(ref_at_entry))
+
+    def apply(self, z, ref: Optional[Ref] = None, n=None, stream=None, pre=None, post=None):
+        """Inference in place; with pre/post (Lattice) the gaps run in the same launches."""
+        ptr, n, ld = _bunch_args(z, n)
+        if pre is None and post is None:
+            _call("hbl_prelu_apply", ptr, n, ld, self._h, C.byref(ref) if ref is not None else None,
+                  stream or current_stream())
+        else:
+            _call("hbl_prelu_apply_gaps", ptr, n, ld, pre._h if pre else None, self._h,
+                  post._h if post else None, C.byref(ref) if ref is not None else None,
+                  stream or current_stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.hbl_prelu_destroy(self._h)
             self._h = None
 
     def __del__(self):
