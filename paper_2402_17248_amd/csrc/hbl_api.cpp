@@ -1260,8 +1260,8 @@ int64_t prelu_nparams_of(const hbl_mlp_shape* sh) {
 hbl_status check_prelu_shape(const hbl_mlp_shape* sh) {
     HBL_REQUIRE(sh, "prelu: NULL shape");
     HBL_REQUIRE(sh->n_in == 6 && sh->n_out == 6, "prelu: n_in and n_out must be 6");
-    HBL_REQUIRE(sh->width >= 8 && sh->width <= 64 * kDenseMaxMT, "prelu: width %d outside [8, %d]", sh->width,
-                64 * kDenseMaxMT);
+    HBL_REQUIRE(sh->width >= 8 && sh->width <= kDenseMaxWidth, "prelu: width %d outside [8, %d]", sh->width,
+                kDenseMaxWidth);
     HBL_REQUIRE(sh->hidden >= 1 && sh->hidden <= kDenseMaxHidden, "prelu: hidden %d outside [1, %d]", sh->hidden,
                 kDenseMaxHidden);
     return HBL_OK;

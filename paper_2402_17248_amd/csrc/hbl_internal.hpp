@@ -112,7 +112,7 @@ hipError_t launch_eval_loss(const double* zin, const double* zout, int64_t ld, i
                             hipStream_t s);
 
 // Wide PReLU surrogate (hidden width W <= 1024, 1..7 hidden layers).
-constexpr int kDenseMaxMT = 16;          // Wp / 64 for Wp <= 1024
+constexpr int kDenseMaxWidth = 1024;
 constexpr int kDenseMaxHidden = 7;
 struct DenseShape {
     int32_t width, hidden;

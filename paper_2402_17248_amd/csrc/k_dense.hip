@@ -18,11 +18,11 @@
 // 4 consecutive out-features of one particle and the bf16 result row is
 // written with 8-byte stores.  Workgroup = 4 waves; a wave owns NT x 16
 // particles (NT = 4: a 256-particle tile per workgroup) and all MT x 16
-// out-features of its workgroup's M block; the M block's weights stream
-// through LDS in K chunks of 64 (double-buffered, the next chunk loaded into
-// registers while the current one feeds the matrix cores) and are shared by
-// the four waves; each wave loads its particles' activations straight from
-// memory (16 B per lane, 64 contiguous bytes per particle row).
+// out-features of its workgroup's M block.  Both operands stream through LDS
+// in K chunks of 32 with the direct-to-LDS load (no registers held for the
+// chunks in flight) through a ring of 4 stages: chunks k + 1 .. k + 3 are in
+// flight while chunk k feeds the matrix cores; the M block's weights are
+// shared by the four waves, each wave stages its own particles.
 //
 // Matrix-core layout (16x16x32, lane l, g = l / 16, r = l % 16):
 //   A (16 x 32): row r, k = 8g .. 8g+7;  B (32 x 16): column r, k = 8g .. 8g+7
@@ -40,8 +40,7 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kNT = 4;                         // 16-particle MFMA tiles per wave
-constexpr int kKc = 64;                        // K chunk staged in LDS
-constexpr int kSegRow = kKc / 8 + 1;           // 16-B units per LDS row (+1 pad)
+constexpr int kKc = 32;                        // K chunk staged in LDS
 
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -79,17 +78,20 @@ __global__ void k_pack_f32(const float* __restrict__ src, int n, float* __restri
 
 // ------------------------------------------------------------ input layer
 // 6 -> W on the vector ALU in FP32 (the network input needs more than bf16's
-// 8 bits): block of 64 particles; the normalised inputs go through LDS, then
-// the 256 threads write the 64 activation rows with coalesced 16-B stores.
-constexpr int kInP = 64;
+// 8 bits).  Block of 256 particles: each thread forms one particle's
+// normalised input into LDS; then thread t keeps the weights of feature
+// group t % G (8 features, G = Wp/8) in registers and walks the particles
+// of its set t / G, so consecutive threads write consecutive 16-B pieces of
+// one activation row.
+constexpr int kInP = 256;
 
 template <bool GAPS, bool CHROM>
 __global__ __launch_bounds__(kBlock) void k_dense_input(const double* __restrict__ z, int64_t nend, int64_t ld,
                                                         int64_t p0, DenseImage im, DenseNorm nm,
                                                         LatticeView pre, uint16_t* __restrict__ x) {
-    __shared__ float xs[kInP][7];
+    __shared__ float xs[kInP][6];
     const int tid = threadIdx.x;
-    if (tid < kInP) {
+    {
         const int64_t i = p0 + (int64_t)blockIdx.x * kInP + tid;
         float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (i < nend) {
@@ -104,27 +106,28 @@ __global__ __launch_bounds__(kBlock) void k_dense_input(const double* __restrict
         for (int j = 0; j < 6; ++j) xs[tid][j] = v[j];
     }
     __syncthreads();
-    const int groups = im.wp / 8;
+    const int groups = im.wp / 8, sets = kBlock / groups;
+    const int gq = tid % groups, set = tid / groups;
+    if (set >= sets) return;                  // no barrier follows
+    float w[8][6], b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        b[j] = im.b0[gq * 8 + j];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) w[j][c] = im.w0[(gq * 8 + j) * 6 + c];
+    }
     const float a0 = im.slope[0];
-    uint16_t* xb = x + (int64_t)blockIdx.x * kInP * im.wp;
-    for (int idx = tid; idx < kInP * groups; idx += kBlock) {
-        const int q = idx / groups, gq = idx - q * groups;
-        uint32_t w[4];
+    uint16_t* xb = x + (int64_t)blockIdx.x * kInP * im.wp + gq * 8;
+    for (int q = set; q < kInP; q += sets) {
+        float h[8];
 #pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-            float h[2];
+        for (int j = 0; j < 8; ++j) {
+            float acc = b[j];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int o = gq * 8 + j + u;
-                const float* wr = im.w0 + o * 6;
-                float acc = im.b0[o];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) acc = fmaf(wr[c], xs[q][c], acc);
-                h[u] = prelu(acc, a0);
-            }
-            w[j / 2] = pack2(h[0], h[1]);
+            for (int c = 0; c < 6; ++c) acc = fmaf(w[j][c], xs[q][c], acc);
+            h[j] = prelu(acc, a0);
         }
-        *(u32x4*)(xb + (int64_t)q * im.wp + gq * 8) = u32x4{w[0], w[1], w[2], w[3]};
+        *(u32x4*)(xb + (int64_t)q * im.wp) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
     }
 }
 
@@ -143,40 +146,62 @@ struct LayerArgs {
 
 enum { kEpiHidden = 0, kEpiOut = 1 };
 
+// LDS tiles hold 64-byte rows (one K chunk of 32 bf16) with the 16-B
+// pieces of row R stored at position piece ^ swz(R): any 16 consecutive rows
+// read at one piece hit distinct 16-B bank groups, for 8 as well as for 16
+// lanes per LDS cycle, so the matrix-core operand reads are conflict-free.
+constexpr int kStages = 4;                     // LDS ring: chunks k+1..k+3 in flight
+__device__ __forceinline__ int swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
+
+// 16 rows x 64 B of a row-major bf16 matrix (row stride K elements) into
+// 1 KB of LDS with the direct-to-LDS load: lane L fills position L % 4 of
+// row L / 4, i.e. loads piece (L % 4) ^ swz(row) of that row.
+__device__ __forceinline__ void dma_rows16(const uint16_t* src_row0, int K, int row_base, int k0,
+                                           __attribute__((address_space(3))) void* lds, int lane) {
+    const int rr = lane >> 2, piece = (lane & 3) ^ swz(row_base + rr);
+    __builtin_amdgcn_global_load_lds(src_row0 + (int64_t)rr * K + k0 + piece * 8, lds, 16, 0, 0);
+}
+
+// s_waitcnt with only the vector-memory counter: at most n loads outstanding.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 template <int MT, int EPI, bool GAPS, bool CHROM>
-__global__ __launch_bounds__(kBlock) void k_dense_layer(LayerArgs a, DenseNorm nm, LatticeView post) {
-    constexpr int ROWS = MT * 16, SEGS = ROWS * (kKc / 8), PER = (SEGS + kBlock - 1) / kBlock;
-    __shared__ u32x4 As[2][ROWS][kSegRow];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dense_layer(LayerArgs a, DenseNorm nm,
+                                                                                                LatticeView post) {
+    constexpr int ROWS = MT * 16;                       // out-features of this M block
+    constexpr int PROWS = kWaves * kNT * 16;            // particles of this tile
+    constexpr int A_BYTES = ROWS * 64, B_BYTES = PROWS * 64, STAGE = A_BYTES + B_BYTES;
+    // direct-to-LDS loads per wave per chunk: the M block's MT pieces of 1 KB
+    // dealt over the waves (a wave past the last piece reloads it, so that
+    // every wave issues the same count), and its own kNT pieces of particles
+    constexpr int A_PER_WAVE = (MT + kWaves - 1) / kWaves, PER_CHUNK = A_PER_WAVE + kNT;
+    __shared__ __attribute__((aligned(1024))) char smem[kStages * STAGE];
     int m, tile;
     tile_of(blockIdx.x, a.mblocks, m, tile);
-    if (tile >= a.tiles) return;                       // whole workgroup: no barrier follows
+    if (tile >= a.tiles) return;                        // whole workgroup: no barrier follows
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r = lane & 15;
     const int K = a.K;
     const uint16_t* wblk = a.w + (int64_t)m * ROWS * K;
-    const int64_t row0 = (int64_t)tile * (kWaves * kNT * 16) + wave * (kNT * 16) + r;
-    const uint16_t* xr = a.x + row0 * K + g * 8;       // + nt * 16 * K + k
+    const int64_t wrow0 = (int64_t)tile * PROWS + wave * (kNT * 16);   // this wave's first particle row
+    const uint16_t* xw = a.x + wrow0 * K;
+    typedef __attribute__((address_space(3))) char lds_char;
+    lds_char* sm = (lds_char*)smem;
 
-    u32x4 pa[PER];
-    auto load_a = [&](int k0) {
+    auto issue = [&](int kc) {
+        lds_char* A = sm + (kc % kStages) * STAGE;
+        lds_char* B = A + A_BYTES + wave * (kNT * 16 * 64);
+        const int k0 = kc * kKc;
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int s = tid + i * kBlock;
-            if (SEGS % kBlock == 0 || s < SEGS) pa[i] = *(const u32x4*)(wblk + (int64_t)(s >> 3) * K + k0 + (s & 7) * 8);
+        for (int i = 0; i < A_PER_WAVE; ++i) {
+            const int j = min(wave + i * kWaves, MT - 1);
+            dma_rows16(wblk + (int64_t)(j * 16) * K, K, j * 16, k0, A + j * 1024, lane);
         }
-    };
-    auto store_a = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int s = tid + i * kBlock;
-            if (SEGS % kBlock == 0 || s < SEGS) As[buf][s >> 3][s & 7] = pa[i];
-        }
-    };
-    u32x4 pb[2][kNT];
-    auto load_b = [&](int k0) {
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) pb[ks][nt] = *(const u32x4*)(xr + (int64_t)nt * 16 * K + k0 + ks * 32);
+        for (int i = 0; i < kNT; ++i) dma_rows16(xw + (int64_t)(i * 16) * K, K, i * 16, k0, B + i * 1024, lane);
     };
 
     f32x4 acc[MT][kNT];
@@ -185,36 +210,69 @@ __global__ __launch_bounds__(kBlock) void k_dense_layer(LayerArgs a, DenseNorm n
 #pragma unroll
         for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    load_a(0);
-    store_a(0);
-    load_b(0);
-    __syncthreads();
-    const int nk = K / kKc;
-    for (int kc = 0; kc < nk; ++kc) {
-        const int buf = kc & 1;
-        u32x4 cb[2][kNT];
+    // operands of one chunk, read from LDS into registers
+    struct Ops {
+        bf16x8 a[MT];
+        bf16x8 b[kNT];
+    };
+    auto read_ops = [&](int kc, Ops& o) {
+        const lds_char* A = sm + (kc % kStages) * STAGE;
+        const lds_char* B = A + A_BYTES + wave * (kNT * 16 * 64);
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) cb[ks][nt] = pb[ks][nt];
-        if (kc + 1 < nk) {
-            load_a((kc + 1) * kKc);
-            load_b((kc + 1) * kKc);
+        for (int nt = 0; nt < kNT; ++nt) {
+            const int pr = nt * 16 + r;
+            o.b[nt] = *(const __attribute__((address_space(3))) bf16x8*)(B + pr * 64 + ((g ^ swz(pr)) * 16));
         }
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const bf16x8 av = __builtin_bit_cast(bf16x8, As[buf][mt * 16 + r][ks * 4 + g]);
-#pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        av, __builtin_bit_cast(bf16x8, cb[ks][nt]), acc[mt][nt], 0, 0, 0);
-            }
+        for (int mt = 0; mt < MT; ++mt) {
+            const int ar = mt * 16 + r;
+            o.a[mt] = *(const __attribute__((address_space(3))) bf16x8*)(A + ar * 64 + ((g ^ swz(ar)) * 16));
         }
-        if (kc + 1 < nk) store_a(buf ^ 1);
-        __syncthreads();
+    };
+    auto products = [&](const Ops& o) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a[mt], o.b[nt], acc[mt][nt], 0, 0, 0);
+    };
+    const int nk = K / kKc;                             // even: Wp is a multiple of 64
+    // make chunk c readable: this wave's loads of it have landed (only the
+    // loads of the chunks after it may be pending) and its reads of chunk
+    // c - 1 are done; after the barrier the same holds for every wave, so
+    // chunk c - 1's stage takes the loads of chunk c + 3.
+    auto sync_for = [&](int c) {
+        if (c + 2 < nk) wait_vm<2 * PER_CHUNK>();
+        else if (c + 1 < nk) wait_vm<PER_CHUNK>();
+        else wait_vm<0>();
+        __builtin_amdgcn_s_waitcnt(0xC07F);             // lgkmcnt(0) only
+        asm volatile("s_barrier" ::: "memory");        // a fence here would wait for every chunk in flight
+        if (c + kStages - 1 < nk) issue(c + kStages - 1);
+    };
+
+#pragma unroll
+    for (int kc = 0; kc < kStages - 1; ++kc)
+        if (kc < nk) issue(kc);
+    Ops o0, o1;
+    sync_for(0);
+    read_ops(0, o0);
+    // chunk kc's operands are in flight into o0; the next chunk's reads
+    // overlap chunk kc's products, and so on (the last pair is peeled so that
+    // no branch joins reads in flight with reads completed)
+    auto half = [&](int c, Ops& next, const Ops& cur) {
+        sync_for(c);
+        read_ops(c, next);
+        products(cur);
+        __builtin_amdgcn_sched_group_barrier(0x100, kNT + MT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MT * kNT, 0);
+    };
+    for (int kc = 0; kc + 2 < nk; kc += 2) {
+        half(kc + 1, o1, o0);
+        half(kc + 2, o0, o1);
     }
+    half(nk - 1, o1, o0);
+    products(o1);
+    const int64_t row0 = wrow0 + r;
 
     if (EPI == kEpiHidden) {
         const float s = *a.slope;
@@ -263,11 +321,20 @@ hipError_t launch_hidden_mt(const LayerArgs& a, hipStream_t s) {
 }
 
 typedef hipError_t (*HiddenLauncher)(const LayerArgs&, hipStream_t);
-const HiddenLauncher kHidden[kDenseMaxMT] = {
+constexpr int kMaxMT = 12;      // accumulators MT x NT x 4 <= 192 stay in the AGPR file
+const HiddenLauncher kHidden[kMaxMT] = {
     launch_hidden_mt<1>, launch_hidden_mt<2>, launch_hidden_mt<3>, launch_hidden_mt<4>,
     launch_hidden_mt<5>, launch_hidden_mt<6>, launch_hidden_mt<7>, launch_hidden_mt<8>,
-    launch_hidden_mt<9>, launch_hidden_mt<10>, launch_hidden_mt<11>, launch_hidden_mt<12>,
-    launch_hidden_mt<13>, launch_hidden_mt<14>, launch_hidden_mt<15>, launch_hidden_mt<16>};
+    launch_hidden_mt<9>, launch_hidden_mt<10>, launch_hidden_mt<11>, launch_hidden_mt<12>};
+
+// M block of a W x W layer: the largest MT <= kMaxMT dividing Wp / 16 (Wp is
+// a multiple of 64, so 4 always divides it).
+int hidden_mt(int wp) {
+    const int tiles = wp / 16;
+    for (int mt = kMaxMT; mt >= 1; --mt)
+        if (tiles % mt == 0) return mt;
+    return 1;
+}
 
 }  // namespace
 
@@ -302,7 +369,7 @@ int dense_tile_rows() { return kWaves * kNT * 16; }
 hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape& sh, const DenseImage& im,
                               const DenseNorm& nm, const LatticeView& pre, const LatticeView& post,
                               uint16_t* buf0, uint16_t* buf1, int64_t chunk, hipStream_t s) {
-    const int Wp = im.wp, H = sh.hidden, MT = Wp / 64;
+    const int Wp = im.wp, H = sh.hidden, MT = hidden_mt(Wp);
     const int tile = dense_tile_rows();
     const bool gaps = pre.n > 0 || post.n > 0;
     const bool chrom = pre.chromatic || post.chromatic;
@@ -322,7 +389,7 @@ hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape
         for (int l = 1; l < H; ++l) {
             LayerArgs a{};
             a.x = xin; a.w = im.w[l]; a.bias = im.b[l]; a.slope = im.slope + l; a.y = yout;
-            a.K = Wp; a.Mp = Wp; a.mblocks = 4; a.tiles = tiles;
+            a.K = Wp; a.Mp = Wp; a.mblocks = Wp / (16 * MT); a.tiles = tiles;
             hipError_t e = kHidden[MT - 1](a, s);
             if (e != hipSuccess) return e;
             uint16_t* t = xin; xin = yout; yout = t;
