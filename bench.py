@@ -424,6 +424,52 @@ def lens_optimisation_study(args, log):
             "moment_driven_lenses": mom_lenses, "eps_nx_fine_step_moment_driven": fine_mom}
 
 
+# §4.3: inference of 1e7 particles on one A100 took 1.12 s per stage for the
+# 5 x 900 networks (stages 1-3) and 494 ms for the 3 x 700 ones (stages 4-15),
+# 63.2 ns per particle and stage averaged over the 15 stages.
+PAPER_A100_S_PER_1E7 = {(900, 5): 1.12, (700, 3): 0.494}
+PAPER_A100_NS_AVG = 63.2
+
+
+def paper_shape_study(log):
+    """The paper's own network shapes (PReLU, 5 x 900 and 3 x 700) on the C4
+    inference workload (1e7 particles): inference time, dense-layer rate on
+    the matrix cores, and the 15-stage average the paper quotes."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+
+    N = W.C4_INFER_N
+    wl = W.c3_stage(n=8)
+    sd = np.asarray(wl.bunch.sigma)
+    norm = np.concatenate([0.0 * sd, sd, 0.0 * sd, sd])
+    z = hbl.new_bunch(N)
+    out = {}
+    for width, hidden in ((900, 5), (700, 3)):
+        net = hbl.PreluNet(width, hidden, W.mlp_init_seed(0))
+        net.set_norm(norm)
+        hbl.fill_gaussian(z, W.C4_INFER_SEED, (0.0,) * 6, wl.bunch.sigma, n=N)
+        t = time_events(torch, lambda: net.apply(z, n=N), 5)
+        fl = net.flops_per_particle()
+        tflops = fl * N / t / 1e12
+        out[f"{hidden}x{width}"] = {
+            "ms_per_1e7": t * 1e3, "ns_per_particle": t / N * 1e9, "flop_per_particle": fl,
+            "dense_tflops": tflops, "mfma_frac": tflops / BF16_PEAK_TFLOPS,
+            "paper_a100_ms_per_1e7": PAPER_A100_S_PER_1E7[(width, hidden)] * 1e3,
+            "ratio_to_paper_a100": PAPER_A100_S_PER_1E7[(width, hidden)] / t}
+        net.close()
+    avg = (3 * out["5x900"]["ns_per_particle"] + 12 * out["3x700"]["ns_per_particle"]) / 15
+    out["avg_15_stages_ns_per_particle"] = avg
+    out["paper_a100_avg_ns_per_particle"] = PAPER_A100_NS_AVG
+    log(f"paper-shaped PReLU surrogates on 1e7 particles: 5x900 {out['5x900']['ms_per_1e7']:.1f} ms "
+        f"({out['5x900']['dense_tflops']:.0f} TFLOP/s, {out['5x900']['mfma_frac']:.0%} of MFMA peak), "
+        f"3x700 {out['3x700']['ms_per_1e7']:.1f} ms ({out['3x700']['dense_tflops']:.0f} TFLOP/s); "
+        f"15-stage average {avg:.2f} ns/particle/stage (paper, A100: {PAPER_A100_NS_AVG} ns)")
+    return out
+
+
 def chain_equal_error(args, wl, chain, dt_sur, step_fn, log):
     """The staged chain at equal error: on the first 1e6 particles of the
     benchmark bunch, the emittance error of the surrogate chain and of the
@@ -582,11 +628,12 @@ def main():
         equal = chain_equal_error(args, wl, chain, dt_sur, time_chain, log)
         configs = config_studies(log)
 
-    single = single_chrom = lens_opt = None
+    single = single_chrom = lens_opt = paper_shapes = None
     if not args.no_single_stage:
         single, _ = single_stage_study(args, log)
         single_chrom, _ = single_stage_study(args, log, chromatic=True)
         lens_opt = lens_optimisation_study(args, log)
+        paper_shapes = paper_shape_study(log)
 
     # ---- dominant kernel: surrogate inference with the gaps fused (k_mlp_infer,
     # one launch per stage pass), timed inside the timed steps above
@@ -626,6 +673,7 @@ def main():
         "single_stage_c4": single,
         "single_stage_c4_chromatic": single_chrom,
         "lens_optimisation": lens_opt,
+        "paper_shaped_surrogates": paper_shapes,
         "particle_element_pushes_per_s": chain.n_elements() * n / dt_sur,
         "roofline": {"bound": "alu", "achieved": alu_achieved, "peak": VALU_PEAK_TSLOTS,
                      "unit": "T VALU slots/s", "frac": alu_achieved / VALU_PEAK_TSLOTS,
