@@ -320,6 +320,25 @@ hbl_status hbl_prelu_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_latt
                                 const hbl_prelu_net* m, const hbl_lattice* post, hbl_ref* ref,
                                 hbl_stream stream);
 
+/* SYNC.  Loss (Eq. 4, normalised units) and gradient of one batch at the
+ * current parameters and normalisation, without updating: idx (host, batch
+ * indices into the pairs, 1 <= batch <= 16384), grad (host, num_params
+ * floats, flat layout), loss (host).  Forward as inference, keeping the bf16
+ * pre-activations and activations; the output error, every back-propagated
+ * error and the activations enter bf16 matrix-core products with FP32
+ * accumulation (weight gradients as products over the batch, including the
+ * bias through a constant-one activation row); slope gradients are FP32
+ * sums over the batch. */
+hbl_status hbl_prelu_loss_grad(hbl_prelu_net* m, const double* zin, const double* zout, int64_t ld,
+                               const int32_t* idx, int32_t batch, float* grad, double* loss,
+                               hbl_stream stream);
+/* Train as hbl_surrogate_train (normalisation from the training split, Adam
+ * reset, half-cosine learning rate, Fisher-Yates epoch order, test loss per
+ * epoch), entirely on the device; batch any size in [1, 16384] (§4.2 uses
+ * 1200).  SYNC at the end; loss_log as for hbl_surrogate_train. */
+hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zout, int64_t n_pairs,
+                           int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

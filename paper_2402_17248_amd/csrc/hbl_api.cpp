@@ -1246,6 +1246,18 @@ struct hbl_prelu_net {
     bool has_norm;
     bool has_stage;
     double dE_MeV, L, gamma_in;
+    // training state, allocated on first use
+    float* d_m;               // Adam moments
+    float* d_v;
+    float* d_grad;
+    uint16_t* d_wt;           // transposed bf16 weights of layers 1..H-1, [wp][wp] each
+    char* d_train;            // DenseTrainBufs arrays (one allocation)
+    int32_t* d_idx;           // batch indices for loss_grad
+    double* d_loss;           // loss accumulators
+    int32_t train_bp, train_B;
+    int64_t loss_slots;
+    DenseTrainBufs tb;
+    int64_t step;
 };
 
 namespace {
@@ -1269,7 +1281,8 @@ hbl_status check_prelu_shape(const hbl_mlp_shape* sh) {
 
 void prelu_free(hbl_prelu_net* m) {
     if (!m) return;
-    void* ptrs[] = {m->d_params, m->d_image, m->d_buf[0], m->d_buf[1]};
+    void* ptrs[] = {m->d_params, m->d_image, m->d_buf[0], m->d_buf[1], m->d_m,   m->d_v,
+                    m->d_grad,   m->d_wt,    m->d_train,  m->d_idx,    m->d_loss};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete m;
@@ -1466,6 +1479,264 @@ hbl_status hbl_prelu_apply(double* z, int64_t n, int64_t ld, const hbl_prelu_net
 hbl_status hbl_prelu_apply_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre, const hbl_prelu_net* m,
                                 const hbl_lattice* post, hbl_ref* ref, hbl_stream stream) {
     return prelu_apply_impl(z, n, ld, pre, m, post, ref, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- wide PReLU training
+namespace {
+
+uint16_t* const* prelu_wt(const hbl_prelu_net* m, uint16_t** wt) {
+    const int64_t wp = m->im.wp;
+    for (int l = 0; l <= kDenseMaxHidden; ++l) wt[l] = nullptr;
+    for (int l = 1; l < m->shape.hidden; ++l) wt[l] = m->d_wt + (int64_t)(l - 1) * wp * wp;
+    return wt;
+}
+
+// Training buffers for batches of B samples (grow-only in the padded size).
+hbl_status prelu_train_buffers(hbl_prelu_net* m, int32_t B, int64_t loss_slots, hipStream_t s) {
+    const int tile = dense_tile_rows();
+    const int32_t bp = (B + tile - 1) / tile * tile;
+    const int64_t wp = m->im.wp, H = m->shape.hidden;
+    const int32_t np = (int32_t)((wp + 1 + tile - 1) / tile * tile);
+    if (!m->d_m) {
+        HBL_HIP(hipMalloc((void**)&m->d_m, sizeof(float) * m->nparams));
+        HBL_HIP(hipMalloc((void**)&m->d_v, sizeof(float) * m->nparams));
+        HBL_HIP(hipMalloc((void**)&m->d_grad, sizeof(float) * m->nparams));
+        if (H > 1) HBL_HIP(hipMalloc((void**)&m->d_wt, sizeof(uint16_t) * (H - 1) * wp * wp));
+        HBL_HIP(hipMemset(m->d_m, 0, sizeof(float) * m->nparams));
+        HBL_HIP(hipMemset(m->d_v, 0, sizeof(float) * m->nparams));
+    }
+    if (loss_slots > m->loss_slots) {
+        if (m->d_loss) { HBL_HIP(hipStreamSynchronize(s)); (void)hipFree(m->d_loss); m->d_loss = nullptr; }
+        HBL_HIP(hipMalloc((void**)&m->d_loss, sizeof(double) * loss_slots));
+        m->loss_slots = loss_slots;
+    }
+    if (bp > m->train_bp) {
+        if (m->d_train) { HBL_HIP(hipStreamSynchronize(s)); (void)hipFree(m->d_train); m->d_train = nullptr; }
+        if (m->d_idx) { (void)hipFree(m->d_idx); m->d_idx = nullptr; }
+        size_t off = 0;
+        auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+        DenseTrainBufs t{};
+        size_t o_x0t = take(2ull * 256 * bp), o_h[kDenseMaxHidden], o_v[kDenseMaxHidden], o_ht[kDenseMaxHidden];
+        for (int l = 0; l < H; ++l) {
+            o_h[l] = take(2ull * bp * wp);
+            o_v[l] = take(2ull * bp * wp);
+            o_ht[l] = take(2ull * np * bp);
+        }
+        size_t o_dv0 = take(2ull * bp * wp), o_dv1 = take(2ull * bp * wp), o_dvt = take(2ull * wp * bp);
+        size_t o_dyt = take(2ull * 16 * bp), o_dy = take(4ull * 8 * bp), o_lossp = take(4ull * bp);
+        size_t o_part = take(4ull * kDensePartMax * kDenseMaxHidden);
+        HBL_HIP(hipMalloc((void**)&m->d_train, off));
+        HBL_HIP(hipMemset(m->d_train, 0, off));
+        HBL_HIP(hipMalloc((void**)&m->d_idx, sizeof(int32_t) * bp));
+        char* b = m->d_train;
+        t.x0t = (uint16_t*)(b + o_x0t);
+        for (int l = 0; l < H; ++l) {
+            t.h[l] = (uint16_t*)(b + o_h[l]);
+            t.v[l] = (uint16_t*)(b + o_v[l]);
+            t.ht[l] = (uint16_t*)(b + o_ht[l]);
+        }
+        t.dv[0] = (uint16_t*)(b + o_dv0);
+        t.dv[1] = (uint16_t*)(b + o_dv1);
+        t.dvt = (uint16_t*)(b + o_dvt);
+        t.dyt = (uint16_t*)(b + o_dyt);
+        t.dy = (float*)(b + o_dy);
+        t.lossp = (float*)(b + o_lossp);
+        t.part = (float*)(b + o_part);
+        t.np = np;
+        m->tb = t;
+        m->train_bp = bp;
+        m->train_B = -1;
+    }
+    m->tb.bp = bp;
+    if (B != m->train_B) {
+        m->tb.B = B;
+        HBL_HIP(launch_dense_fill_ones(m->tb, (int32_t)wp, (int32_t)H, s));
+        m->train_B = B;
+    }
+    return HBL_OK;
+}
+
+DenseNorm prelu_norm(const hbl_prelu_net* m) {
+    DenseNorm nm;
+    for (int j = 0; j < 6; ++j) {
+        nm.mu_in[j] = m->norm[j];
+        nm.sd_in[j] = m->norm[6 + j];
+        nm.mu_out[j] = m->norm[12 + j];
+        nm.sd_out[j] = m->norm[18 + j];
+    }
+    return nm;
+}
+
+hbl_status prelu_repack_all(hbl_prelu_net* m, hipStream_t s) {
+    const DenseShape sh{m->shape.width, m->shape.hidden};
+    uint16_t* wt[kDenseMaxHidden + 1];
+    HBL_HIP(launch_dense_pack(m->d_params, sh, m->im, s));
+    if (m->d_wt) HBL_HIP(launch_dense_pack_t(m->d_params, sh, m->im.wp, prelu_wt(m, wt), s));
+    return HBL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_prelu_loss_grad(hbl_prelu_net* m, const double* zin, const double* zout, int64_t ld,
+                               const int32_t* idx, int32_t batch, float* grad, double* loss, hbl_stream stream) {
+    clear_error();
+    HBL_REQUIRE(m && idx && grad && loss, "prelu_loss_grad: NULL argument");
+    HBL_REQUIRE(batch >= 1 && batch <= 16384, "prelu_loss_grad: batch %d outside [1, 16384]", batch);
+    if (hbl_status st = check_bunch(zin, 1, ld, "prelu_loss_grad(in)")) return st;
+    if (hbl_status st = check_bunch(zout, 1, ld, "prelu_loss_grad(out)")) return st;
+    HBL_REQUIRE(zin && zout, "prelu_loss_grad: NULL pairs");
+    for (int32_t q = 0; q < batch; ++q)
+        HBL_REQUIRE(idx[q] >= 0 && idx[q] < ld, "prelu_loss_grad: index %d out of range", idx[q]);
+    if (!m->has_norm) { set_error(HBL_ESTATE, "prelu_loss_grad: no normalisation set"); return HBL_ESTATE; }
+    hipStream_t s = (hipStream_t)stream;
+    if (hbl_status st = prelu_train_buffers(m, batch, 1, s)) return st;
+    if (hbl_status st = prelu_repack_all(m, s)) return st;
+    DenseTrainBufs tb = m->tb;
+    tb.idx = m->d_idx;
+    uint16_t* wt[kDenseMaxHidden + 1];
+    HBL_HIP(hipMemcpyAsync(m->d_idx, idx, sizeof(int32_t) * batch, hipMemcpyHostToDevice, s));
+    HBL_HIP(hipMemsetAsync(m->d_loss, 0, sizeof(double), s));
+    HBL_HIP(launch_dense_train_step(zin, zout, ld, DenseShape{m->shape.width, m->shape.hidden}, m->im, prelu_wt(m, wt),
+                                    prelu_norm(m), tb, m->d_params, m->d_grad, m->d_loss, 1.0 / (6.0 * batch), s));
+    HBL_HIP(hipMemcpyAsync(grad, m->d_grad, sizeof(float) * m->nparams, hipMemcpyDeviceToHost, s));
+    HBL_HIP(hipMemcpyAsync(loss, m->d_loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    HBL_HIP(hipStreamSynchronize(s));
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zout, int64_t n_pairs, int64_t ld,
+                           const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream) {
+    clear_error();
+    HBL_REQUIRE(m && cfg, "prelu_train: NULL argument");
+    if (hbl_status st = check_bunch(zin, n_pairs, ld, "prelu_train(in)")) return st;
+    if (hbl_status st = check_bunch(zout, n_pairs, ld, "prelu_train(out)")) return st;
+    HBL_REQUIRE(cfg->batch >= 1 && cfg->batch <= 16384, "prelu_train: batch %d outside [1, 16384]", cfg->batch);
+    HBL_REQUIRE(cfg->epochs >= 0 && cfg->epochs <= 1000000, "prelu_train: bad epoch count");
+    HBL_REQUIRE(isfinite(cfg->lr) && cfg->lr > 0, "prelu_train: lr must be > 0");
+    HBL_REQUIRE(isfinite(cfg->lr_final) && cfg->lr_final > 0, "prelu_train: lr_final must be > 0");
+    HBL_REQUIRE(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1, "prelu_train: betas must be in [0,1)");
+    HBL_REQUIRE(isfinite(cfg->eps) && cfg->eps > 0, "prelu_train: eps must be > 0");
+    HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "prelu_train: train_frac must be in (0, 1]");
+    HBL_REQUIRE(n_pairs <= INT32_MAX, "prelu_train: at most 2^31-1 pairs");
+    const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
+    const int64_t n_test = n_pairs - n_train;
+    HBL_REQUIRE(n_train >= cfg->batch, "prelu_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);
+    hipStream_t s = (hipStream_t)stream;
+    double mi[6], ci[21], mo[6], co[21];
+    if (hbl_status st = hbl_moments(zin, n_train, ld, mi, ci, stream)) return st;
+    if (hbl_status st = hbl_moments(zout, n_train, ld, mo, co, stream)) return st;
+    double norm[24];
+    for (int j = 0; j < 6; ++j) {
+        const int d = j * 6 - j * (j - 1) / 2;
+        norm[j] = mi[j];
+        norm[6 + j] = sqrt(ci[d]);
+        norm[12 + j] = mo[j];
+        norm[18 + j] = sqrt(co[d]);
+    }
+    if (hbl_status st = check_norm(norm)) {
+        set_error(HBL_EINVAL, "prelu_train: a coordinate has zero spread in the training split");
+        return st;
+    }
+    memcpy(m->norm, norm, sizeof norm);
+    m->has_norm = true;
+    const int64_t epochs = cfg->epochs;
+    if (hbl_status st = prelu_train_buffers(m, cfg->batch, 2 * (epochs > 0 ? epochs : 1), s)) return st;
+    HBL_HIP(hipMemsetAsync(m->d_m, 0, sizeof(float) * m->nparams, s));
+    HBL_HIP(hipMemsetAsync(m->d_v, 0, sizeof(float) * m->nparams, s));
+    HBL_HIP(hipMemsetAsync(m->d_loss, 0, sizeof(double) * 2 * (epochs > 0 ? epochs : 1), s));
+    if (hbl_status st = prelu_repack_all(m, s)) return st;
+    m->step = 0;
+    const DenseShape sh{m->shape.width, m->shape.hidden};
+    const DenseNorm nm = prelu_norm(m);
+    uint16_t* wt[kDenseMaxHidden + 1];
+    prelu_wt(m, wt);
+    const int64_t steps_per_epoch = n_train / cfg->batch;
+    int64_t planned = epochs * steps_per_epoch;
+    if (cfg->max_steps >= 0 && cfg->max_steps < planned) planned = cfg->max_steps;
+    auto lr_at = [&](int64_t t) {
+        if (planned <= 1 || cfg->lr_final == cfg->lr) return (double)cfg->lr;
+        const double ph = 3.14159265358979323846 * (double)(t - 1) / (double)(planned - 1);
+        return (double)cfg->lr_final + 0.5 * ((double)cfg->lr - (double)cfg->lr_final) * (1.0 + cos(ph));
+    };
+    int32_t* h_perm[2] = {nullptr, nullptr};
+    int32_t* d_perm[2] = {nullptr, nullptr};
+    int32_t* d_test = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hbl_status st = HBL_OK;
+    auto fail = [&](hbl_status code, const char* what, hipError_t e) {
+        set_error(code, "prelu_train: %s: %s", what, hipGetErrorString(e));
+        st = code;
+    };
+    for (int k = 0; k < 2 && st == HBL_OK; ++k) {
+        hipError_t e = hipHostMalloc((void**)&h_perm[k], sizeof(int32_t) * n_train, 0);
+        if (e == hipSuccess) e = hipMalloc((void**)&d_perm[k], sizeof(int32_t) * n_train);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) fail(HBL_ENOMEM, "order buffers", e);
+    }
+    if (st == HBL_OK && n_test > 0) {
+        std::vector<int32_t> ti(n_test);
+        for (int64_t i = 0; i < n_test; ++i) ti[i] = (int32_t)(n_train + i);
+        hipError_t e = hipMalloc((void**)&d_test, sizeof(int32_t) * n_test);
+        if (e == hipSuccess) e = hipMemcpy(d_test, ti.data(), sizeof(int32_t) * n_test, hipMemcpyHostToDevice);
+        if (e != hipSuccess) fail(HBL_ENOMEM, "test indices", e);
+    }
+    std::vector<int64_t> steps_done(epochs > 0 ? epochs : 1, 0);
+    for (int64_t ep = 0; ep < epochs && st == HBL_OK; ++ep) {
+        const int k = (int)(ep & 1);
+        hipError_t e = hipEventSynchronize(ev[k]);
+        if (e != hipSuccess) { fail(HBL_EHIP, "event wait", e); break; }
+        epoch_order(h_perm[k], n_train, cfg->shuffle_seed, ep);
+        e = hipMemcpyAsync(d_perm[k], h_perm[k], sizeof(int32_t) * n_train, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[k], s);
+        if (e != hipSuccess) { fail(HBL_EHIP, "order upload", e); break; }
+        DenseTrainBufs tb = m->tb;
+        for (int64_t step = 0; step < steps_per_epoch; ++step) {
+            if (cfg->max_steps >= 0 && m->step >= cfg->max_steps) break;
+            m->step += 1;
+            tb.idx = d_perm[k] + step * cfg->batch;
+            e = launch_dense_train_step(zin, zout, ld, sh, m->im, wt, nm, tb, m->d_params, m->d_grad,
+                                        m->d_loss + 2 * ep, 1.0 / (6.0 * cfg->batch), s);
+            if (e == hipSuccess)
+                e = launch_dense_adam_pack(m->d_params, m->d_m, m->d_v, m->d_grad, m->nparams, m->step,
+                                           (float)lr_at(m->step), cfg->beta1, cfg->beta2, cfg->eps, sh, m->im,
+                                           m->d_wt ? wt : nullptr, s);
+            if (e != hipSuccess) { fail(HBL_EHIP, "step launch", e); break; }
+            steps_done[ep] += 1;
+        }
+        if (st != HBL_OK) break;
+        // test loss over the held-out pairs, in batches of the training size
+        for (int64_t t0 = 0; t0 < n_test; t0 += cfg->batch) {
+            const int32_t nb = (int32_t)std::min<int64_t>(cfg->batch, n_test - t0);
+            DenseTrainBufs te = m->tb;
+            te.idx = d_test + t0;
+            te.B = nb;
+            e = launch_dense_train_step(zin, zout, ld, sh, m->im, wt, nm, te, m->d_params, nullptr,
+                                        m->d_loss + 2 * ep + 1, 1.0 / (6.0 * (double)n_test), s);
+            if (e != hipSuccess) { fail(HBL_EHIP, "test loss launch", e); break; }
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (st == HBL_OK && e != hipSuccess) fail(HBL_EHIP, "training", e);
+    if (st == HBL_OK && loss_log && epochs > 0) {
+        std::vector<double> acc(2 * epochs);
+        e = hipMemcpy(acc.data(), m->d_loss, sizeof(double) * acc.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) fail(HBL_EHIP, "loss readback", e);
+        for (int64_t ep = 0; ep < epochs && st == HBL_OK; ++ep) {
+            loss_log[2 * ep] = steps_done[ep] ? (float)(acc[2 * ep] / (double)steps_done[ep]) : 0.0f;
+            loss_log[2 * ep + 1] = (float)acc[2 * ep + 1];
+        }
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+        if (d_perm[k]) (void)hipFree(d_perm[k]);
+        if (h_perm[k]) (void)hipHostFree(h_perm[k]);
+    }
+    if (d_test) (void)hipFree(d_test);
+    return st;
 }
 
 }  // extern "C"

@@ -137,6 +137,44 @@ hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape
                               const DenseNorm& nm, const LatticeView& pre, const LatticeView& post,
                               uint16_t* buf0, uint16_t* buf1, int64_t chunk, hipStream_t s);
 
+// Training of the wide network (batch rows padded to bp, a multiple of the
+// 256-row tile; rows >= B carry zero error).
+constexpr int kDensePartMax = 4096;      // slope-gradient partial sums per layer
+struct DenseTrainBufs {
+    int32_t bp, B, np;                   // padded batch, batch, rows of the transposed activations
+    const int32_t* idx;                  // [B] sample indices of this step
+    uint16_t* x0t;                       // [256][bp] network input, transposed; row 6 = 1 (bias)
+    uint16_t* h[kDenseMaxHidden];        // [bp][wp] hidden activations
+    uint16_t* v[kDenseMaxHidden];        // [bp][wp] pre-activations
+    uint16_t* ht[kDenseMaxHidden];       // [np][bp] activations transposed; row wp = 1 (bias)
+    uint16_t* dv[2];                     // [bp][wp] dL/dv ping-pong
+    uint16_t* dvt;                       // [wp][bp] dL/dv transposed
+    uint16_t* dyt;                       // [16][bp] output error, transposed (bf16)
+    float* dy;                           // [bp][8] output error
+    float* lossp;                        // [bp] squared error per sample
+    float* part;                         // [kDenseMaxHidden][kDensePartMax]
+};
+// Flat parameter offsets (as the public layout): A_l, b_l, slope_l.
+struct DenseOffsets {
+    int64_t A[kDenseMaxHidden + 1], b[kDenseMaxHidden + 1], slope[kDenseMaxHidden];
+};
+DenseOffsets dense_offsets(const DenseShape& sh);
+hipError_t launch_dense_pack_t(const float* params, const DenseShape& sh, int32_t wp, uint16_t* const* wt,
+                               hipStream_t s);
+hipError_t launch_dense_fill_ones(const DenseTrainBufs& tb, int32_t wp, int32_t hidden, hipStream_t s);
+// Forward with stored activations, loss and full gradient of one batch;
+// adds sum(loss) * loss_scale to *loss_acc.  grad_out may be nullptr for a
+// loss-only (evaluation) pass.
+hipError_t launch_dense_train_step(const double* zin, const double* zout, int64_t ld, const DenseShape& sh,
+                                   const DenseImage& im, uint16_t* const* wt, const DenseNorm& nm,
+                                   const DenseTrainBufs& tb, const float* params, float* grad_out,
+                                   double* loss_acc, double loss_scale, hipStream_t s);
+// Adam on the FP32 parameters, the updated values also written into the
+// operand images (im, and the transposed W x W images wt[1..H-1]).
+hipError_t launch_dense_adam_pack(float* p, float* m, float* v, const float* g, int64_t n, int64_t t, float lr,
+                                  float b1, float b2, float eps, const DenseShape& sh, const DenseImage& im,
+                                  uint16_t* const* wt, hipStream_t s);
+
 // Per-device library workspace (grow-only, freed at exit).
 double* workspace(size_t bytes);
 

@@ -142,9 +142,25 @@ struct LayerArgs {
     // output layer: particles p0 + row for rows with p0 + row < nend
     double* z;
     int64_t ld, p0, nend;
+    // training (rows = batch samples, ldt = padded batch)
+    uint16_t* v;           // [rows][Mp] pre-activations (forward) / read (backward)
+    uint16_t* yt;          // [Mp][ldt] transposed output, or nullptr
+    int ldt;
+    float* part;           // one partial sum per workgroup (backward: slope gradient)
+    // gradient GEMM: rows o < W of the M operand; "particle" rows k < gcols are
+    // weight columns (grad[o * gcols + k]), row bias_row carries the bias (gradb[o])
+    float* grad;
+    float* gradb;
+    int W, gcols, bias_row;
 };
 
-enum { kEpiHidden = 0, kEpiOut = 1 };
+// kEpiHidden: y = bf16(prelu(acc + b)).  kEpiOut: de-normalised FP64 output.
+// kEpiTrain: kEpiHidden, also keeping v = bf16(acc + b) and the transposed y.
+// kEpiBwd: acc = dL/dh of the layer below (weights transposed); writes its
+//   dL/dv = acc * prelu'(v) as y and transposed, and the workgroup's share
+//   of the slope gradient, sum of acc * v over v <= 0.
+// kEpiGrad: acc = weight gradient [o][k] (o: rows, k: "particle" rows), FP32.
+enum { kEpiHidden = 0, kEpiOut = 1, kEpiTrain = 2, kEpiBwd = 3, kEpiGrad = 4 };
 
 // LDS tiles hold 64-byte rows (one K chunk of 32 bf16) with the 16-B
 // pieces of row R stored at position piece ^ swz(R): any 16 consecutive rows
@@ -182,7 +198,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     __shared__ __attribute__((aligned(1024))) char smem[kStages * STAGE];
     int m, tile;
     tile_of(blockIdx.x, a.mblocks, m, tile);
-    if (tile >= a.tiles) return;                        // whole workgroup: no barrier follows
+    if (tile >= a.tiles) {                              // whole workgroup: no barrier follows
+        if (EPI == kEpiBwd && threadIdx.x == 0) a.part[blockIdx.x] = 0.0f;
+        return;
+    }
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r = lane & 15;
     const int K = a.K;
     const uint16_t* wblk = a.w + (int64_t)m * ROWS * K;
@@ -274,7 +293,78 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     products(o1);
     const int64_t row0 = wrow0 + r;
 
-    if (EPI == kEpiHidden) {
+    if (EPI == kEpiTrain) {
+        const float s = *a.slope;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int o = m * ROWS + mt * 16 + 4 * g;
+            const f32x4 bb = *(const f32x4*)(a.bias + o);
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) {
+                const int64_t p = row0 + nt * 16;
+                const f32x4 v = acc[mt][nt] + bb;
+                const float h0 = prelu(v[0], s), h1 = prelu(v[1], s), h2 = prelu(v[2], s), h3 = prelu(v[3], s);
+                *(u32x2*)(a.y + p * a.Mp + o) = u32x2{pack2(h0, h1), pack2(h2, h3)};
+                *(u32x2*)(a.v + p * a.Mp + o) = u32x2{pack2(v[0], v[1]), pack2(v[2], v[3])};
+                if (a.yt) {
+                    const float hh[4] = {h0, h1, h2, h3};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        a.yt[(int64_t)(o + i) * a.ldt + p] = __builtin_bit_cast(uint16_t, (__bf16)hh[i]);
+                }
+            }
+        }
+    } else if (EPI == kEpiBwd) {
+        const float s = *a.slope;
+        float sp = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int k = m * ROWS + mt * 16 + 4 * g;
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) {
+                const int64_t p = row0 + nt * 16;
+                const f32x4 dh = acc[mt][nt];
+                const u32x2 vw = *(const u32x2*)(a.v + p * a.Mp + k);
+                const float vv[4] = {__uint_as_float(vw[0] << 16), __uint_as_float(vw[0] & 0xffff0000u),
+                                     __uint_as_float(vw[1] << 16), __uint_as_float(vw[1] & 0xffff0000u)};
+                float dv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool pos = vv[i] > 0.0f;
+                    dv[i] = pos ? dh[i] : s * dh[i];
+                    sp += pos ? 0.0f : dh[i] * vv[i];
+                    a.yt[(int64_t)(k + i) * a.ldt + p] = __builtin_bit_cast(uint16_t, (__bf16)dv[i]);
+                }
+                *(u32x2*)(a.y + p * a.Mp + k) = u32x2{pack2(dv[0], dv[1]), pack2(dv[2], dv[3])};
+            }
+        }
+        // workgroup sum of the slope-gradient share (fixed order)
+        for (int off = 32; off >= 1; off >>= 1) sp += __shfl_xor(sp, off, 64);
+        __shared__ float red[kWaves];
+        if (lane == 0) red[wave] = sp;
+        __syncthreads();
+        if (tid == 0) {
+            float t = 0.0f;
+            for (int w = 0; w < kWaves; ++w) t += red[w];
+            a.part[blockIdx.x] = t;
+        }
+    } else if (EPI == kEpiGrad) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int o = m * ROWS + mt * 16 + 4 * g;
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) {
+                const int64_t k = row0 + nt * 16;
+                const f32x4 gv = acc[mt][nt];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (o + i >= a.W) continue;
+                    if (k < a.gcols) a.grad[(int64_t)(o + i) * a.gcols + k] = gv[i];
+                    else if (k == a.bias_row) a.gradb[o + i] = gv[i];
+                }
+            }
+        }
+    } else if (EPI == kEpiHidden) {
         const float s = *a.slope;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -311,21 +401,292 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     }
 }
 
-template <int MT>
-hipError_t launch_hidden_mt(const LayerArgs& a, hipStream_t s) {
+// ------------------------------------------------------------ training
+// Training kernels below work on one 256-row block of the batch and on 64
+// features at a time: thread (f, pl) = (tid % 8, tid / 8) forms features
+// 8f .. 8f+7 of rows pl, pl + 32, ... (16-B row-major stores), the same
+// values go into a [64 features][256 rows] LDS tile, which the block then
+// writes to the transposed array as whole 512-B rows.
+constexpr int kFeatChunk = 64;
+__device__ __forceinline__ void store_tile_t(const uint16_t (*tile)[kInP + 8], uint16_t* dst_t, int64_t ldt,
+                                             int k0, int64_t p0) {
+    // 64 rows x 256 columns of bf16: 2048 pieces of 16 B, 8 per thread
+    for (int piece = threadIdx.x; piece < kFeatChunk * (kInP / 8); piece += kBlock) {
+        const int kk = piece / (kInP / 8), c8 = (piece % (kInP / 8)) * 8;
+        const u32x4 v = *(const u32x4*)&tile[kk][c8];
+        *(u32x4*)(dst_t + (int64_t)(k0 + kk) * ldt + p0 + c8) = v;
+    }
+}
+
+// Input layer of a training batch: sample p < B is pair idx[p] (rows >= B
+// take a zero input); stores the transposed bf16 network input (rows 0..5 of
+// x0t), the pre-activations, the activations and their transpose.
+__global__ __launch_bounds__(kBlock) void k_train_input(const double* __restrict__ zin, int64_t ld,
+                                                        DenseTrainBufs tb, DenseImage im, DenseNorm nm) {
+    __shared__ float xs[kInP][6];
+    __shared__ __attribute__((aligned(16))) uint16_t tile[kFeatChunk][kInP + 8];
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * kInP;
+    {
+        const int64_t p = p0 + tid;
+        float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (p < tb.B) {
+            P6 q;
+            load6(zin, ld, tb.idx[p], q);
+            const double pv[6] = {q.x, q.y, q.t, q.px, q.py, q.pt};
+#pragma unroll
+            for (int j = 0; j < 6; ++j) v[j] = (float)((pv[j] - nm.mu_in[j]) / nm.sd_in[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            xs[tid][j] = v[j];
+            tb.x0t[(int64_t)j * tb.bp + p] = __builtin_bit_cast(uint16_t, (__bf16)v[j]);
+        }
+    }
+    const int f = tid % 8, pl = tid / 8;
+    const float a0 = im.slope[0];
+    for (int k0 = 0; k0 < im.wp; k0 += kFeatChunk) {
+        __syncthreads();                                  // xs ready / previous tile written out
+        const int kf = k0 + 8 * f;
+        float w[8][6], b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            b[j] = im.b0[kf + j];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) w[j][c] = im.w0[(kf + j) * 6 + c];
+        }
+        for (int q = pl; q < kInP; q += kBlock / 8) {
+            float h[8], v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                float acc = b[j];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc = fmaf(w[j][c], xs[q][c], acc);
+                v[j] = acc;
+                h[j] = prelu(acc, a0);
+                tile[8 * f + j][q] = __builtin_bit_cast(uint16_t, (__bf16)h[j]);
+            }
+            const int64_t off = (p0 + q) * im.wp + kf;
+            *(u32x4*)(tb.h[0] + off) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+            *(u32x4*)(tb.v[0] + off) = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+        }
+        __syncthreads();
+        store_tile_t(tile, tb.ht[0], tb.bp, k0, p0);
+    }
+}
+
+// Output layer forward and its error (Eq. 4): one wave per sample; yhat =
+// W_H h + b_H (bf16 weights and activations, FP32 sums), dy = scale (yhat -
+// y) with y the normalised target; rows >= B give zero error.
+__global__ __launch_bounds__(kBlock) void k_train_out_fwd(const double* __restrict__ zout, int64_t ld,
+                                                          DenseTrainBufs tb, DenseImage im, DenseNorm nm,
+                                                          const uint16_t* __restrict__ hlast, uint16_t* __restrict__ wH,
+                                                          const float* __restrict__ bH, float scale) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = lane * 8; k < im.wp; k += 64 * 8) {
+        const u32x4 hv = *(const u32x4*)(hlast + (int64_t)p * im.wp + k);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const u32x4 wv = *(const u32x4*)(wH + (int64_t)j * im.wp + k);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc[j] = fmaf(__uint_as_float(wv[e] << 16), __uint_as_float(hv[e] << 16), acc[j]);
+                acc[j] = fmaf(__uint_as_float(wv[e] & 0xffff0000u), __uint_as_float(hv[e] & 0xffff0000u), acc[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+        for (int off = 32; off >= 1; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+    if (lane == 0) {
+        float l2 = 0.0f;
+        for (int j = 0; j < 6; ++j) {
+            float d = 0.0f;
+            if (p < tb.B) {
+                const double y = (zout[(int64_t)j * ld + tb.idx[p]] - nm.mu_out[j]) / nm.sd_out[j];
+                d = (acc[j] + bH[j]) - (float)y;
+            }
+            l2 = fmaf(d, d, l2);
+            tb.dy[p * 8 + j] = scale * d;
+            tb.dyt[(int64_t)j * tb.bp + p] = __builtin_bit_cast(uint16_t, (__bf16)(scale * d));
+        }
+        tb.lossp[p] = l2;
+    }
+}
+
+// Back through the output layer and the last PReLU: dh = W_H^T dy, dv =
+// dh prelu'(v); the workgroup's share of the slope gradient to part.
+__global__ __launch_bounds__(kBlock) void k_train_out_bwd(DenseTrainBufs tb, DenseImage im,
+                                                          const uint16_t* __restrict__ wH,
+                                                          const uint16_t* __restrict__ vlast,
+                                                          const float* __restrict__ slope, uint16_t* __restrict__ dv,
+                                                          float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) uint16_t tile[kFeatChunk][kInP + 8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int f = tid % 8, pl = tid / 8;
+    const int64_t p0 = (int64_t)blockIdx.x * kInP;
+    const float a = *slope;
+    float sp = 0.0f;
+    for (int k0 = 0; k0 < im.wp; k0 += kFeatChunk) {
+        const int kf = k0 + 8 * f;
+        float w[8][6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const u32x4 wv = *(const u32x4*)(wH + (int64_t)j * im.wp + kf);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                w[2 * e][j] = __uint_as_float(wv[e] << 16);
+                w[2 * e + 1][j] = __uint_as_float(wv[e] & 0xffff0000u);
+            }
+        }
+        __syncthreads();                                  // previous tile written out
+        for (int q = pl; q < kInP; q += kBlock / 8) {
+            const int64_t p = p0 + q;
+            const int64_t off = p * im.wp + kf;
+            const u32x4 vv = *(const u32x4*)(vlast + off);
+            float dy[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) dy[j] = tb.dy[p * 8 + j];
+            float d[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                float dh = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) dh = fmaf(w[e][j], dy[j], dh);
+                const float v = (e & 1) ? __uint_as_float(vv[e >> 1] & 0xffff0000u) : __uint_as_float(vv[e >> 1] << 16);
+                const bool pos = v > 0.0f;
+                d[e] = pos ? dh : a * dh;
+                sp += pos ? 0.0f : dh * v;
+                tile[8 * f + e][q] = __builtin_bit_cast(uint16_t, (__bf16)d[e]);
+            }
+            *(u32x4*)(dv + off) = u32x4{pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]), pack2(d[6], d[7])};
+        }
+        __syncthreads();
+        store_tile_t(tile, tb.dvt, tb.bp, k0, p0);
+    }
+    for (int off = 32; off >= 1; off >>= 1) sp += __shfl_xor(sp, off, 64);
+    __shared__ float red[kWaves];
+    if (lane == 0) red[wave] = sp;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int w2 = 0; w2 < kWaves; ++w2) t += red[w2];
+        part[blockIdx.x] = t;
+    }
+}
+
+// Loss and slope gradients of one step: one workgroup, fixed summation order
+// (thread t sums entries t, t + 256, ...; then a tree over the threads).
+struct FinishArgs {
+    int64_t slope_off[kDenseMaxHidden];
+    int32_t nparts[kDenseMaxHidden];
+    int32_t hidden;
+};
+__device__ float block_sum(float x, float* red) {
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const float t = red[0];
+    __syncthreads();
+    return t;
+}
+__global__ __launch_bounds__(kBlock) void k_train_finish(DenseTrainBufs tb, FinishArgs fa, float* grad,
+                                                         double* loss_acc, double scale) {
+    __shared__ float red[kBlock];
+    const int t = threadIdx.x;
+    float l = 0.0f;
+    for (int p = t; p < tb.B; p += kBlock) l += tb.lossp[p];
+    l = block_sum(l, red);
+    if (t == 0) *loss_acc += (double)l * scale;
+    if (!grad) return;                                 // uniform: the whole block returns
+    for (int h = 0; h < fa.hidden; ++h) {
+        float x = 0.0f;
+        for (int q = t; q < fa.nparts[h]; q += kBlock) x += tb.part[h * kDensePartMax + q];
+        x = block_sum(x, red);
+        if (t == 0) grad[fa.slope_off[h]] = x;
+    }
+}
+
+__global__ void k_fill_row(uint16_t* row, int n, int valid, uint16_t one) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) row[i] = i < valid ? one : (uint16_t)0;
+}
+
+__global__ void k_pack_bf16_t(const float* __restrict__ src, int rows, int cols, uint16_t* __restrict__ dst,
+                              int rows_p, int cols_p) {
+    // dst[c][r] = src[r][c] (dst: cols_p x rows_p), zero padding
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows_p * cols_p) return;
+    const int c = (int)(i / rows_p), r = (int)(i % rows_p);
+    const float v = (r < rows && c < cols) ? src[(int64_t)r * cols + c] : 0.0f;
+    dst[i] = __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// Adam (bias-corrected) on every parameter, writing the updated value
+// straight into the operand images as well: first-layer FP32, biases and
+// slopes FP32, W x W weights bf16 in both orientations, output layer bf16.
+struct WtImages {
+    uint16_t* w[kDenseMaxHidden + 1];
+};
+__global__ void k_dense_adam_pack(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                  const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
+                                  float c1, float c2, DenseOffsets off, DenseImage im, WtImages wt, int H, int W) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    int l = 0;
+    while (l < H && i >= off.A[l + 1]) ++l;            // i lies in layer l's tensors
+    const int wp = im.wp;
+    if (l < H && i == off.slope[l]) {
+        im.slope[l] = pi;
+    } else if (i >= off.b[l]) {
+        const int o = (int)(i - off.b[l]);
+        if (l == 0) im.b0[o] = pi;
+        else im.b[l][o] = pi;
+    } else {
+        const int64_t q = i - off.A[l];
+        const int ni = l == 0 ? 6 : W;
+        const int o = (int)(q / ni), k = (int)(q % ni);
+        if (l == 0) {
+            im.w0[o * 6 + k] = pi;
+        } else {
+            const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pi);
+            im.w[l][(int64_t)o * wp + k] = b;
+            if (l < H && wt.w[l]) wt.w[l][(int64_t)k * wp + o] = b;
+        }
+    }
+}
+
+int layer_grid(const LayerArgs& a) { return a.mblocks * ((a.tiles + 7) / 8) * 8; }
+
+template <int MT, int EPI>
+hipError_t launch_layer_mt(const LayerArgs& a, hipStream_t s) {
     const LatticeView none{};
     const DenseNorm nm{};
-    const int grid = a.mblocks * ((a.tiles + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_dense_layer<MT, kEpiHidden, false, false>), dim3(grid), dim3(kBlock), 0, s, a, nm, none);
+    hipLaunchKernelGGL((k_dense_layer<MT, EPI, false, false>), dim3(layer_grid(a)), dim3(kBlock), 0, s, a, nm, none);
     return hipGetLastError();
 }
 
-typedef hipError_t (*HiddenLauncher)(const LayerArgs&, hipStream_t);
+typedef hipError_t (*LayerLauncher)(const LayerArgs&, hipStream_t);
 constexpr int kMaxMT = 12;      // accumulators MT x NT x 4 <= 192 stay in the AGPR file
-const HiddenLauncher kHidden[kMaxMT] = {
-    launch_hidden_mt<1>, launch_hidden_mt<2>, launch_hidden_mt<3>, launch_hidden_mt<4>,
-    launch_hidden_mt<5>, launch_hidden_mt<6>, launch_hidden_mt<7>, launch_hidden_mt<8>,
-    launch_hidden_mt<9>, launch_hidden_mt<10>, launch_hidden_mt<11>, launch_hidden_mt<12>};
+template <int EPI>
+struct LayerTable {
+    static constexpr LayerLauncher f[kMaxMT] = {
+        launch_layer_mt<1, EPI>, launch_layer_mt<2, EPI>, launch_layer_mt<3, EPI>, launch_layer_mt<4, EPI>,
+        launch_layer_mt<5, EPI>, launch_layer_mt<6, EPI>, launch_layer_mt<7, EPI>, launch_layer_mt<8, EPI>,
+        launch_layer_mt<9, EPI>, launch_layer_mt<10, EPI>, launch_layer_mt<11, EPI>, launch_layer_mt<12, EPI>};
+};
 
 // M block of a W x W layer: the largest MT <= kMaxMT dividing Wp / 16 (Wp is
 // a multiple of 64, so 4 always divides it).
@@ -390,7 +751,7 @@ hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape
             LayerArgs a{};
             a.x = xin; a.w = im.w[l]; a.bias = im.b[l]; a.slope = im.slope + l; a.y = yout;
             a.K = Wp; a.Mp = Wp; a.mblocks = Wp / (16 * MT); a.tiles = tiles;
-            hipError_t e = kHidden[MT - 1](a, s);
+            hipError_t e = LayerTable<kEpiHidden>::f[MT - 1](a, s);
             if (e != hipSuccess) return e;
             uint16_t* t = xin; xin = yout; yout = t;
         }
@@ -408,6 +769,124 @@ hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+}  // namespace hbl
+
+namespace hbl {
+
+DenseOffsets dense_offsets(const DenseShape& sh) {
+    DenseOffsets o{};
+    int64_t off = 0;
+    for (int l = 0; l <= sh.hidden; ++l) {
+        const int64_t ni = l == 0 ? 6 : sh.width, no = l == sh.hidden ? 6 : sh.width;
+        o.A[l] = off;
+        o.b[l] = off + no * ni;
+        off += no * (ni + 1);
+        if (l < sh.hidden) o.slope[l] = off++;
+    }
+    return o;
+}
+
+hipError_t launch_dense_pack_t(const float* params, const DenseShape& sh, int32_t wp, uint16_t* const* wt,
+                               hipStream_t s) {
+    const DenseOffsets o = dense_offsets(sh);
+    for (int l = 1; l < sh.hidden; ++l) {
+        const int64_t cnt = (int64_t)wp * wp;
+        hipLaunchKernelGGL(k_pack_bf16_t, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, params + o.A[l],
+                           sh.width, sh.width, wt[l], wp, wp);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_fill_ones(const DenseTrainBufs& tb, int32_t wp, int32_t hidden, hipStream_t s) {
+    const uint16_t one = 0x3F80;   // bf16 1.0
+    const dim3 g((tb.bp + 255) / 256);
+    hipLaunchKernelGGL(k_fill_row, g, dim3(256), 0, s, tb.x0t + (int64_t)6 * tb.bp, tb.bp, tb.B, one);
+    for (int l = 0; l < hidden; ++l)
+        hipLaunchKernelGGL(k_fill_row, g, dim3(256), 0, s, tb.ht[l] + (int64_t)wp * tb.bp, tb.bp, tb.B, one);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_train_step(const double* zin, const double* zout, int64_t ld, const DenseShape& sh,
+                                   const DenseImage& im, uint16_t* const* wt, const DenseNorm& nm,
+                                   const DenseTrainBufs& tb, const float* params, float* grad,
+                                   double* loss_acc, double loss_scale, hipStream_t s) {
+    (void)params;
+    // a training batch is only a few 256-row tiles: M blocks of 2 MFMA tiles
+    // (32 rows) give the products enough workgroups to spread over the chip
+    const int wp = im.wp, H = sh.hidden, MT = 2;
+    const int tiles = tb.bp / dense_tile_rows();
+    const DenseOffsets off = dense_offsets(sh);
+    FinishArgs fa{};
+    fa.hidden = H;
+    // ---- forward, keeping what the backward pass needs
+    hipLaunchKernelGGL(k_train_input, dim3(tb.bp / kInP), dim3(kBlock), 0, s, zin, ld, tb, im, nm);
+    for (int l = 1; l < H; ++l) {
+        LayerArgs a{};
+        a.x = tb.h[l - 1]; a.w = im.w[l]; a.bias = im.b[l]; a.slope = im.slope + l; a.y = tb.h[l];
+        a.v = tb.v[l]; a.yt = tb.ht[l]; a.ldt = tb.bp;
+        a.K = wp; a.Mp = wp; a.mblocks = wp / (16 * MT); a.tiles = tiles;
+        hipError_t e = LayerTable<kEpiTrain>::f[MT - 1](a, s);
+        if (e != hipSuccess) return e;
+    }
+    const float scale = 2.0f / (float)(tb.B * 6);
+    hipLaunchKernelGGL(k_train_out_fwd, dim3(tb.bp / kWaves), dim3(kBlock), 0, s, zout, ld, tb, im, nm,
+                       tb.h[H - 1], im.w[H], im.b[H], scale);
+    if (grad) {
+        // ---- output layer: weight and bias gradients, then back into the last hidden layer
+        {
+            LayerArgs a{};
+            a.x = tb.ht[H - 1]; a.w = tb.dyt; a.K = tb.bp; a.Mp = 16; a.mblocks = 1;
+            a.tiles = tb.np / dense_tile_rows();
+            a.grad = grad + off.A[H]; a.gradb = grad + off.b[H]; a.W = 6; a.gcols = sh.width; a.bias_row = wp;
+            hipError_t e = LayerTable<kEpiGrad>::f[0](a, s);
+            if (e != hipSuccess) return e;
+        }
+        int cur = 0;
+        hipLaunchKernelGGL(k_train_out_bwd, dim3(tb.bp / kInP), dim3(kBlock), 0, s, tb, im, im.w[H], tb.v[H - 1],
+                           im.slope + (H - 1), tb.dv[cur], tb.part + (int64_t)(H - 1) * kDensePartMax);
+        fa.nparts[H - 1] = tb.bp / kInP;
+        // ---- hidden layers, top down
+        for (int l = H - 1; l >= 1; --l) {
+            LayerArgs g{};
+            g.x = tb.ht[l - 1]; g.w = tb.dvt; g.K = tb.bp; g.Mp = wp; g.mblocks = wp / (16 * MT);
+            g.tiles = tb.np / dense_tile_rows();
+            g.grad = grad + off.A[l]; g.gradb = grad + off.b[l]; g.W = sh.width; g.gcols = sh.width; g.bias_row = wp;
+            hipError_t e = LayerTable<kEpiGrad>::f[MT - 1](g, s);
+            if (e != hipSuccess) return e;
+            LayerArgs b{};
+            b.x = tb.dv[cur]; b.w = wt[l]; b.slope = im.slope + (l - 1); b.y = tb.dv[cur ^ 1]; b.v = tb.v[l - 1];
+            b.yt = tb.dvt; b.ldt = tb.bp; b.part = tb.part + (int64_t)(l - 1) * kDensePartMax;
+            b.K = wp; b.Mp = wp; b.mblocks = wp / (16 * MT); b.tiles = tiles;
+            fa.nparts[l - 1] = layer_grid(b);
+            e = LayerTable<kEpiBwd>::f[MT - 1](b, s);
+            if (e != hipSuccess) return e;
+            cur ^= 1;
+        }
+        // ---- first layer: gradient against the transposed network input
+        {
+            LayerArgs a{};
+            a.x = tb.x0t; a.w = tb.dvt; a.K = tb.bp; a.Mp = wp; a.mblocks = wp / (16 * MT); a.tiles = 1;
+            a.grad = grad + off.A[0]; a.gradb = grad + off.b[0]; a.W = sh.width; a.gcols = 6; a.bias_row = 6;
+            hipError_t e = LayerTable<kEpiGrad>::f[MT - 1](a, s);
+            if (e != hipSuccess) return e;
+        }
+        for (int h = 0; h < H; ++h) fa.slope_off[h] = off.slope[h];
+    }
+    hipLaunchKernelGGL(k_train_finish, dim3(1), dim3(kBlock), 0, s, tb, fa, grad, loss_acc, loss_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_adam_pack(float* p, float* m, float* v, const float* g, int64_t n, int64_t t, float lr,
+                                  float b1, float b2, float eps, const DenseShape& sh, const DenseImage& im,
+                                  uint16_t* const* wt, hipStream_t s) {
+    const float c1 = (float)(1.0 - pow((double)b1, (double)t)), c2 = (float)(1.0 - pow((double)b2, (double)t));
+    WtImages w{};
+    for (int l = 0; l <= kDenseMaxHidden; ++l) w.w[l] = wt ? wt[l] : nullptr;
+    hipLaunchKernelGGL(k_dense_adam_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, m, v, g, n, lr, b1,
+                       b2, eps, c1, c2, dense_offsets(sh), im, w, sh.hidden, sh.width);
+    return hipGetLastError();
 }
 
 }  // namespace hbl

@@ -106,6 +106,8 @@ def _load():
         "hbl_prelu_set_stage": ([vp, C.POINTER(Element), C.POINTER(Ref)], st),
         "hbl_prelu_apply": ([vp, i64, i64, vp, C.POINTER(Ref), vp], st),
         "hbl_prelu_apply_gaps": ([vp, i64, i64, vp, vp, vp, C.POINTER(Ref), vp], st),
+        "hbl_prelu_loss_grad": ([vp, vp, vp, i64, C.POINTER(C.c_int32), i32, C.POINTER(C.c_float), dp, vp], st),
+        "hbl_prelu_train": ([vp, vp, vp, i64, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp], st),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -382,6 +384,31 @@ class PreluNet:
     def set_stage(self, stage, ref_at_entry: Ref):
         el = stage if isinstance(stage, Element) else element(stage)
         _call("hbl_prelu_set_stage", self._h, C.byref(el), C.byref(ref_at_entry))
+
+    def loss_grad(self, zin, zout, idx, stream=None):
+        import numpy as np
+        pin, _, ld = _bunch_args(zin)
+        pout, _, _ = _bunch_args(zout)
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        _call("hbl_prelu_loss_grad", self._h, pin, pout, ld, idx.ctypes.data_as(C.POINTER(C.c_int32)),
+              len(idx), g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), stream or current_stream())
+        return loss.value, g
+
+    def train(self, zin, zout, n_pairs, batch=1200, epochs=1, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8,
+              train_frac=0.7, shuffle_seed=0, max_steps=-1, lr_final=None, stream=None):
+        import numpy as np
+        pin, _, ld = _bunch_args(zin, n_pairs)
+        pout, _, ldo = _bunch_args(zout, n_pairs)
+        if ldo != ld:
+            raise ValueError("train: input and output pairs need the same leading dimension")
+        cfg = TrainCfg(batch, epochs, max_steps, lr, lr if lr_final is None else lr_final, beta1, beta2, eps,
+                       train_frac, shuffle_seed)
+        log = np.zeros(2 * max(epochs, 1), dtype=np.float32)
+        _call("hbl_prelu_train", self._h, pin, pout, n_pairs, ld, C.byref(cfg),
+              log.ctypes.data_as(C.POINTER(C.c_float)), stream or current_stream())
+        return log[: 2 * epochs].reshape(epochs, 2)
 
     def apply(self, z, ref: Optional[Ref] = None, n=None, stream=None, pre=None, post=None):
         """Inference in place; with pre/post (Lattice) the gaps run in the same launches."""

@@ -1,0 +1,144 @@
+"""GPU training of the paper-shaped PReLU surrogate (§3 Eq. 2-4, §4.2)
+against the oracle's exact FP64 loss and gradient, through the C ABI.
+
+The GPU forward keeps bf16 activations and the backward pass feeds bf16
+errors and activations to the matrix cores (FP32 sums).  Against the exact
+gradient that is a relative error of ~2^-8 per product, averaged over the
+batch: ~1e-2 per weight block, more where a block's gradient sums cancel;
+the loss itself moves by the forward's bf16 rounding (~1e-2 of the outputs'
+spread, squared against O(1) errors at initialisation: ~1e-3 relative)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hbl():
+    from paper_2402_17248_amd import hbl as h
+    return h
+
+
+@pytest.fixture(scope="module")
+def pairs(hbl, orc):
+    """2^13 stage pairs made by the oracle (triplet, then a fine-step stage)."""
+    n = 1 << 13
+    wl = W.c3_stage(n=n, nsub=400)
+    c = orc.fill_gaussian(n, 3, (0.0,) * 6, wl.bunch.sigma)
+    oref = orc.Ref.from_energy(wl.E_MeV)
+    orc.push(c, wl.beamline[0], oref)
+    xin = c.copy()
+    orc.push(c, [wl.beamline[1]], oref)
+    return n, to_dev(xin), to_dev(c), xin, c
+
+
+def blocks(sh):
+    """(name, start, end) of every parameter tensor in the flat layout."""
+    out, off = [], 0
+    for l in range(sh.hidden + 1):
+        ni = 6 if l == 0 else sh.width
+        no = 6 if l == sh.hidden else sh.width
+        out.append((f"A{l}", off, off + no * ni))
+        off += no * ni
+        out.append((f"b{l}", off, off + no))
+        off += no
+        if l < sh.hidden:
+            out.append((f"a{l}", off, off + 1))
+            off += 1
+    return out
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def perturbed(orc, sh, seed):
+    p = orc.prelu_init(sh, seed).copy()
+    rng = np.random.default_rng(seed)
+    for name, a, b in blocks(sh):
+        if name.startswith("a"):
+            p[a] = rng.uniform(0.1, 0.4)           # distinct slopes per layer
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("width,hidden,batch", [(64, 1, 300), (100, 3, 256), (700, 3, 300)])
+def test_loss_grad_matches_oracle(hbl, orc, pairs, width, hidden, batch):
+    n, rec, out, xin, xout = pairs
+    sh = orc.shape(width=width, hidden=hidden)
+    norm = orc.norm_stats(xin, xout, n)
+    net = hbl.PreluNet(width, hidden, 0)
+    p = perturbed(orc, sh, 5)
+    net.set_params(p)
+    net.set_norm(norm)
+    idx = np.random.default_rng(6).choice(n, batch, replace=False).astype(np.int32)
+    loss_g, g = net.loss_grad(rec, out, idx)
+    loss_o, go = orc.prelu_loss_grad(sh, p, norm, xin, xout, idx.astype(np.int64))
+    print(f"{width}x{hidden}: loss {loss_g:.6g} vs {loss_o:.6g}; total rel {rel_fro(g.astype(float), go):.3e}")
+    assert abs(loss_g / loss_o - 1) < 1e-2
+    assert rel_fro(g.astype(np.float64), go) < 3e-2
+    for name, a, b in blocks(sh):
+        r = rel_fro(g[a:b].astype(np.float64), go[a:b])
+        print(f"  {name}: {r:.3e}")
+        assert r < (1e-1 if name.startswith("a") else 5e-2), name
+
+
+def test_gradient_ignores_samples_past_the_batch(hbl, orc, pairs):
+    """A batch that is not a multiple of the 256-row tile: the padded rows
+    contribute nothing (same gradient as the oracle's on exactly these)."""
+    n, rec, out, xin, xout = pairs
+    sh = orc.shape(width=64, hidden=2)
+    norm = orc.norm_stats(xin, xout, n)
+    net = hbl.PreluNet(64, 2, 1)
+    net.set_norm(norm)
+    p = net.get_params()
+    for batch in (1, 255, 257):
+        idx = np.arange(batch, dtype=np.int32) * 7 % n
+        _, g = net.loss_grad(rec, out, idx)
+        _, go = orc.prelu_loss_grad(sh, p, norm, xin, xout, idx.astype(np.int64))
+        assert rel_fro(g.astype(np.float64), go) < 5e-2, batch
+
+
+def test_training_matches_oracle_loop(hbl, orc, pairs):
+    """Three epochs of the library's training against the oracle's loss
+    gradient and Adam driven through the same epoch orders and learning-rate
+    schedule: the parameters move the same way and the losses agree."""
+    n, rec, out, xin, xout = pairs
+    W_, H_, B, E, lr, lr_final = 64, 2, 256, 3, 3e-3, 3e-4
+    sh = orc.shape(width=W_, hidden=H_)
+    net = hbl.PreluNet(W_, H_, 21)
+    p0 = orc.prelu_init(sh, 21)
+    assert np.array_equal(net.get_params(), p0)
+    log = net.train(rec, out, n, batch=B, epochs=E, lr=lr, lr_final=lr_final, shuffle_seed=9)
+    ntr = int(round(0.7 * n))
+    on = orc.norm_stats(xin, xout, ntr)
+    assert np.allclose(net.get_norm(), on, rtol=1e-13, atol=0)
+    steps = ntr // B
+    planned = E * steps
+    p = p0.astype(np.float32)
+    m = np.zeros(len(p))
+    v = np.zeros(len(p))
+    t = 0
+    olog = []
+    for e in range(E):
+        perm = orc.epoch_perm(ntr, 9, e)
+        ls = []
+        for s in range(steps):
+            t += 1
+            loss, g = orc.prelu_loss_grad(sh, p, on, xin, xout, perm[s * B:(s + 1) * B])
+            lr_t = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * (t - 1) / (planned - 1)))
+            p, m, v = orc.adam_step(p, m, v, g, t, lr=lr_t)
+            ls.append(loss)
+        tl, _ = orc.prelu_loss_grad(sh, p, on, xin, xout, np.arange(ntr, n))
+        olog.append((np.mean(ls), tl))
+    olog = np.array(olog)
+    pg = net.get_params().astype(np.float64)
+    moved = np.linalg.norm(p.astype(np.float64) - p0)
+    print("log", log.tolist(), "oracle", olog.tolist(), "param diff / moved",
+          np.linalg.norm(pg - p) / moved)
+    assert np.all(np.isfinite(log))
+    assert log[-1, 1] < 0.7 * log[0, 1]
+    assert np.all(np.abs(log / olog - 1) < 0.1), (log, olog)
+    assert np.linalg.norm(pg - p) < 0.25 * moved
