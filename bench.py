@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=1200, help="training epochs per surrogate")
     ap.add_argument("--pairs", type=int, default=1 << 20)
     ap.add_argument("--lens-epochs", type=int, default=300, help="training epochs of the lens-chain surrogates")
+    ap.add_argument("--prelu-epochs", type=int, default=60,
+                    help="epochs of the paper-shaped 3 x 700 surrogate trained with the paper's recipe")
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -429,6 +431,76 @@ def lens_optimisation_study(args, log):
 # 63.2 ns per particle and stage averaged over the 15 stages.
 PAPER_A100_S_PER_1E7 = {(900, 5): 1.12, (700, 3): 0.494}
 PAPER_A100_NS_AVG = 63.2
+# §4.2: batch 1200, learning rate 1e-4, 1500 epochs; about 2.2 h per stage
+# (5 x 900) and 2 h (3 x 700) on one A100.
+PAPER_BATCH, PAPER_LR, PAPER_EPOCHS = 1200, 1e-4, 1500
+PAPER_A100_TRAIN_H = {(900, 5): 2.2, (700, 3): 2.0}
+
+
+def paper_shape_training(args, log):
+    """Train the paper-shaped networks with the paper's recipe on the C4
+    stage pairs (2^20 pairs of the fine-step stage behind its triplet), then
+    apply the trained 3 x 700 network to the 1e7-particle C4 bunch and
+    compare with the 2000-substep stage."""
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+
+    wl = W.c3_stage()
+    sig, stage = wl.bunch.sigma, wl.beamline[1]
+
+    def through_triplet(n, seed):
+        z = hbl.new_bunch(n)
+        hbl.fill_gaussian(z, seed, (0.0,) * 6, sig, n=n)
+        ref = hbl.Ref.from_energy(wl.E_MeV)
+        hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
+        return z, ref
+
+    npairs = W.C3_PAIR_N
+    zout, ref = through_triplet(npairs, W.C3_PAIR_SEED)
+    zin = hbl.new_bunch(npairs)
+    entry = ref.copy()
+    hbl.apply_stage(zout, stage, ref, record=zin, n=npairs)
+    n_train, _ = W.split_counts(npairs)
+    out = {}
+    trained = None
+    for (width, hidden), epochs in (((700, 3), args.prelu_epochs), ((900, 5), 2)):
+        net = hbl.PreluNet(width, hidden, W.mlp_init_seed(0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        curve = net.train(zin, zout, npairs, batch=PAPER_BATCH, epochs=epochs, lr=PAPER_LR, lr_final=PAPER_LR / 10,
+                          train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps = epochs * (n_train // PAPER_BATCH)
+        per_epoch = dt / epochs
+        out[f"{hidden}x{width}"] = {
+            "epochs": epochs, "seconds": dt, "seconds_per_epoch": per_epoch,
+            "samples_per_s": steps * PAPER_BATCH / dt, "us_per_step_incl_test_loss": dt / steps * 1e6,
+            "final_loss_train_test": [float(v) for v in curve[-1]],
+            "projected_1500_epochs_s": per_epoch * PAPER_EPOCHS,
+            "paper_a100_hours_1500_epochs": PAPER_A100_TRAIN_H[(width, hidden)]}
+        if (width, hidden) == (700, 3):
+            trained = net
+        else:
+            net.close()
+    del zin, zout
+    trained.set_stage(stage, entry)
+    N = W.C4_INFER_N
+    x, r0 = through_triplet(N, W.C4_INFER_SEED)
+    f = x.clone()
+    hbl.apply_stage(f, stage, r0.copy(), n=N)
+    x_s = x.clone()
+    trained.apply(x_s, r0.copy(), n=N)
+    rms, cen, eps = hbl.compare(x_s, f, n=N)
+    out["3x700"]["c4_eps_rel_xyt_vs_2000_substeps"] = eps
+    out["3x700"]["c4_rms_over_sigma"] = rms
+    log(f"paper-recipe training: 3x700 {out['3x700']['epochs']} epochs in {out['3x700']['seconds']:.1f} s "
+        f"({out['3x700']['samples_per_s']:.3g} samples/s; 1500 epochs ~{out['3x700']['projected_1500_epochs_s']:.0f} s, "
+        f"paper A100 ~2 h), final loss {out['3x700']['final_loss_train_test']}; 5x900 "
+        f"{out['5x900']['seconds_per_epoch']:.2f} s/epoch; trained 3x700 on C4 1e7: eps_rel {eps}, rms {rms}")
+    return out
 
 
 def paper_shape_study(log):
@@ -634,6 +706,7 @@ def main():
         single_chrom, _ = single_stage_study(args, log, chromatic=True)
         lens_opt = lens_optimisation_study(args, log)
         paper_shapes = paper_shape_study(log)
+        paper_shapes["training"] = paper_shape_training(args, log)
 
     # ---- dominant kernel: surrogate inference with the gaps fused (k_mlp_infer,
     # one launch per stage pass), timed inside the timed steps above
