@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--prelu-epochs", type=int, default=60,
                     help="epochs of the paper-shaped 3 x 700 surrogate trained with the paper's recipe")
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
+    ap.add_argument("--only-paper-shapes", action="store_true",
+                    help="run only the paper-shaped PReLU surrogate studies (inference and training)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-single-stage", action="store_true",
@@ -603,6 +605,13 @@ def main():
     args = parse()
     if args.pmc_probe:
         pmc_probe(args)
+        return
+    if args.only_paper_shapes:
+        import torch
+        torch.cuda.set_device(0)
+        out = paper_shape_study(log)
+        out["training"] = paper_shape_training(args, log)
+        print(json.dumps({"paper_shaped_surrogates": out}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; there is no multi-GPU path "

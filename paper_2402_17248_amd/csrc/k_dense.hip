@@ -402,8 +402,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 }
 
 // ------------------------------------------------------------ training
-// Training kernels below work on one 256-row block of the batch and on 64
-// features at a time: thread (f, pl) = (tid % 8, tid / 8) forms features
+// Training kernels below work on one 256-row block of the batch and one
+// chunk of 64 features (blockIdx.y): thread (f, pl) = (tid % 8, tid / 8) forms features
 // 8f .. 8f+7 of rows pl, pl + 32, ... (16-B row-major stores), the same
 // values go into a [64 features][256 rows] LDS tile, which the block then
 // writes to the transposed array as whole 512-B rows.
@@ -440,13 +440,14 @@ __global__ __launch_bounds__(kBlock) void k_train_input(const double* __restrict
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             xs[tid][j] = v[j];
-            tb.x0t[(int64_t)j * tb.bp + p] = __builtin_bit_cast(uint16_t, (__bf16)v[j]);
+            if (blockIdx.y == 0) tb.x0t[(int64_t)j * tb.bp + p] = __builtin_bit_cast(uint16_t, (__bf16)v[j]);
         }
     }
     const int f = tid % 8, pl = tid / 8;
     const float a0 = im.slope[0];
-    for (int k0 = 0; k0 < im.wp; k0 += kFeatChunk) {
-        __syncthreads();                                  // xs ready / previous tile written out
+    {
+        const int k0 = blockIdx.y * kFeatChunk;           // this block's 64 features
+        __syncthreads();                                  // xs ready
         const int kf = k0 + 8 * f;
         float w[8][6], b[8];
 #pragma unroll
@@ -529,7 +530,8 @@ __global__ __launch_bounds__(kBlock) void k_train_out_bwd(DenseTrainBufs tb, Den
     const int64_t p0 = (int64_t)blockIdx.x * kInP;
     const float a = *slope;
     float sp = 0.0f;
-    for (int k0 = 0; k0 < im.wp; k0 += kFeatChunk) {
+    {
+        const int k0 = blockIdx.y * kFeatChunk;           // this block's 64 features
         const int kf = k0 + 8 * f;
         float w[8][6];
 #pragma unroll
@@ -541,7 +543,6 @@ __global__ __launch_bounds__(kBlock) void k_train_out_bwd(DenseTrainBufs tb, Den
                 w[2 * e + 1][j] = __uint_as_float(wv[e] & 0xffff0000u);
             }
         }
-        __syncthreads();                                  // previous tile written out
         for (int q = pl; q < kInP; q += kBlock / 8) {
             const int64_t p = p0 + q;
             const int64_t off = p * im.wp + kf;
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_train_out_bwd(DenseTrainBufs tb, Den
     if (tid == 0) {
         float t = 0.0f;
         for (int w2 = 0; w2 < kWaves; ++w2) t += red[w2];
-        part[blockIdx.x] = t;
+        part[blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -821,7 +822,8 @@ hipError_t launch_dense_train_step(const double* zin, const double* zout, int64_
     FinishArgs fa{};
     fa.hidden = H;
     // ---- forward, keeping what the backward pass needs
-    hipLaunchKernelGGL(k_train_input, dim3(tb.bp / kInP), dim3(kBlock), 0, s, zin, ld, tb, im, nm);
+    const dim3 g2(tb.bp / kInP, wp / kFeatChunk);         // row blocks x feature chunks
+    hipLaunchKernelGGL(k_train_input, g2, dim3(kBlock), 0, s, zin, ld, tb, im, nm);
     for (int l = 1; l < H; ++l) {
         LayerArgs a{};
         a.x = tb.h[l - 1]; a.w = im.w[l]; a.bias = im.b[l]; a.slope = im.slope + l; a.y = tb.h[l];
@@ -844,9 +846,9 @@ hipError_t launch_dense_train_step(const double* zin, const double* zout, int64_
             if (e != hipSuccess) return e;
         }
         int cur = 0;
-        hipLaunchKernelGGL(k_train_out_bwd, dim3(tb.bp / kInP), dim3(kBlock), 0, s, tb, im, im.w[H], tb.v[H - 1],
+        hipLaunchKernelGGL(k_train_out_bwd, g2, dim3(kBlock), 0, s, tb, im, im.w[H], tb.v[H - 1],
                            im.slope + (H - 1), tb.dv[cur], tb.part + (int64_t)(H - 1) * kDensePartMax);
-        fa.nparts[H - 1] = tb.bp / kInP;
+        fa.nparts[H - 1] = (int)(g2.x * g2.y);
         // ---- hidden layers, top down
         for (int l = H - 1; l >= 1; --l) {
             LayerArgs g{};
