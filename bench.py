@@ -505,6 +505,48 @@ def paper_shape_training(args, log):
     return out
 
 
+def paper_shape_chain(args, log, wl, time_chain, dt_fine, z_fine):
+    """The staged chain with the paper's own networks: one 3 x 700 PReLU
+    surrogate per stage, trained with the paper's recipe on that stage's
+    pairs, run on the same 2.5e7-particle bunch as the headline chain."""
+    import torch
+
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+    from paper_2402_17248_amd.chain import Chain
+
+    c = Chain(wl.beamline, wl.E_MeV)
+    n = wl.bunch.n
+    t0 = time.perf_counter()
+    losses = []
+    for k in range(c.stage_count):
+        zin, zout = c.make_pairs(k, args.pairs, W.c5_pair_seed(k + 1), wl.bunch.sigma)
+        net = hbl.PreluNet(700, 3, W.mlp_init_seed(k + 1))
+        curve = net.train(zin, zout, args.pairs, batch=PAPER_BATCH, epochs=args.prelu_epochs // 2, lr=PAPER_LR,
+                          lr_final=PAPER_LR / 10, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(k + 1))
+        net.set_stage(c.stage(k), c.entry_ref(k))
+        c.surrogates[k] = net
+        losses.append([float(v) for v in curve[-1]])
+        del zin, zout
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    dt = time_chain(lambda zz: c.run(zz, n=n, use_surrogates=True), 3, 1)
+    zs = hbl.new_bunch(n)
+    hbl.fill_gaussian(zs, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+    c.run(zs, n=n, use_surrogates=True)
+    rms, cen, eps = hbl.compare(zs, z_fine, n=n)
+    del zs
+    out = {"network": "PReLU 6-700-700-700-6 per stage", "epochs_per_stage": args.prelu_epochs // 2,
+           "train_seconds": t_train, "final_loss_train_test": losses, "ms_per_step": dt * 1e3,
+           "particles_per_s": n / dt, "speedup_vs_fine_step_chain": dt_fine / dt,
+           "eps_rel_xyt_vs_fine_step_chain": eps, "rms_over_sigma": rms}
+    log(f"chain with paper-shaped surrogates: {dt * 1e3:.1f} ms/step ({n / dt:.3g} particles/s, "
+        f"{dt_fine / dt:.1f}x the fine-step chain); eps_rel vs fine-step chain {eps}; trained in {t_train:.1f} s")
+    for sur in c.surrogates:
+        sur.close()
+    return out
+
+
 def paper_shape_study(log):
     """The paper's own network shapes (PReLU, 5 x 900 and 3 x 700) on the C4
     inference workload (1e7 particles): inference time, dense-layer rate on
@@ -676,9 +718,13 @@ def main():
         return dt, per_launch
 
     def time_chain(c, steps, warmup):
+        """c: a Chain (run with its fine-step stages) or a callable run(z)."""
         def one():
             hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
-            c.run(z, n=n)
+            if callable(c):
+                c(z)
+            else:
+                c.run(z, n=n)
             hbl.moments_async(z, out27, n=n)
         for _ in range(warmup):
             one()
@@ -703,6 +749,7 @@ def main():
     rms, cen, eps_rel = hbl.compare(zs, z, n=n)
     log(f"surrogate vs fine-step chain: eps_rel x,y,t = {eps_rel}, rms/sigma = {rms}")
     del zs
+    z_fine = z.clone()                  # the fine-step chain's result, kept for the paper-shaped chain
 
     equal = configs = None
     if not args.no_single_stage:
@@ -716,6 +763,8 @@ def main():
         lens_opt = lens_optimisation_study(args, log)
         paper_shapes = paper_shape_study(log)
         paper_shapes["training"] = paper_shape_training(args, log)
+        paper_shapes["chain"] = paper_shape_chain(args, log, wl, time_chain, dt_fine, z_fine)
+    del z_fine
 
     # ---- dominant kernel: surrogate inference with the gaps fused (k_mlp_infer,
     # one launch per stage pass), timed inside the timed steps above
