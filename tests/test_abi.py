@@ -131,3 +131,26 @@ def test_emittances_host_only(hbl):
     bad[0] = float("inf")
     with pytest.raises(hbl.HblError):
         hbl.emittances(bad)
+
+
+@pytest.mark.parametrize("shape,frag", [
+    ((6, 7, 3, 6), "width 7"),
+    ((6, 1025, 3, 6), "width 1025"),
+    ((6, 700, 0, 6), "hidden 0"),
+    ((6, 700, 8, 6), "hidden 8"),
+    ((5, 700, 3, 6), "n_in and n_out"),
+    ((6, 700, 3, 4), "n_in and n_out"),
+])
+def test_prelu_create_rejects_bad_shapes(hbl, shape, frag):
+    h = C.c_void_p()
+    rc = hbl.lib.hbl_prelu_create(C.byref(hbl.MlpShape(*shape)), 0, C.byref(h))
+    assert rc == hbl.HBL_EINVAL and frag in hbl.lib.hbl_last_error().decode()
+    assert h.value is None
+
+
+def test_prelu_calls_reject_null_handles(hbl):
+    n = C.c_int64()
+    assert hbl.lib.hbl_prelu_num_params(None, C.byref(n)) == hbl.HBL_EINVAL
+    assert hbl.lib.hbl_prelu_apply(BAD, 10, 10, None, None, None) == hbl.HBL_EINVAL
+    assert hbl.lib.hbl_prelu_apply(BAD, 10, 9, None, None, None) == hbl.HBL_EINVAL
+    assert hbl.lib.hbl_prelu_set_norm(None, (C.c_double * 24)()) == hbl.HBL_EINVAL

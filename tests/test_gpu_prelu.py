@@ -149,3 +149,23 @@ def test_full_size_sampled(hbl, orc, width, hidden):
     mx, med, frac = compare(g, c, norm)
     print(f"full {width}x{hidden}: max {mx:.3e} median {med:.3e} frac>1e-3 {frac:.4f}")
     assert mx < 5e-3 and med < 1e-6 and frac < 0.01
+
+
+@pytest.mark.parametrize("width,hidden", [(8, 1), (72, 2), (136, 3), (250, 2), (520, 7), (1024, 2)])
+def test_forward_parity_other_widths(hbl, orc, width, hidden):
+    """Widths that pick every kind of M block (4 to 12 MFMA tiles, one to
+    eight blocks per layer), the deepest and the widest network allowed."""
+    sh = orc.shape(width=width, hidden=hidden)
+    m = 700
+    x, norm = bunch(orc, m, 24)
+    p = perturbed(orc, sh, 10)
+    net = hbl.PreluNet(width, hidden, 0)
+    net.set_params(p)
+    net.set_norm(norm)
+    z = to_dev(x)
+    net.apply(z, n=m)
+    g = to_host(z, m)
+    c = orc.prelu_apply(sh, p, norm, x, mode=1)
+    mx, med, frac = compare(g, c, norm)
+    print(f"{width}x{hidden}: max {mx:.3e} median {med:.3e}")
+    assert mx < 5e-3 and med < 1e-6 and frac < 0.01

@@ -64,7 +64,8 @@ def perturbed(orc, sh, seed):
     return p.astype(np.float32)
 
 
-@pytest.mark.parametrize("width,hidden,batch", [(64, 1, 300), (100, 3, 256), (700, 3, 300)])
+@pytest.mark.parametrize("width,hidden,batch", [(64, 1, 300), (100, 3, 256), (700, 3, 300), (136, 3, 400),
+                                                (1024, 2, 256)])
 def test_loss_grad_matches_oracle(hbl, orc, pairs, width, hidden, batch):
     n, rec, out, xin, xout = pairs
     sh = orc.shape(width=width, hidden=hidden)
