@@ -339,6 +339,12 @@ hbl_status hbl_prelu_loss_grad(hbl_prelu_net* m, const double* zin, const double
 hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zout, int64_t n_pairs,
                            int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream);
 
+/* Save / load the network (shape, normalisation, stage, FP32 parameters,
+ * Adam moments when it has trained, step) to a binary file with a checksum.
+ * HBL_EIO on I/O or format errors. */
+hbl_status hbl_prelu_save(const hbl_prelu_net* m, const char* path);
+hbl_status hbl_prelu_load(const char* path, hbl_prelu_net** out);
+
 #ifdef __cplusplus
 }
 #endif

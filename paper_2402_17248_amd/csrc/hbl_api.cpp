@@ -1493,20 +1493,29 @@ uint16_t* const* prelu_wt(const hbl_prelu_net* m, uint16_t** wt) {
     return wt;
 }
 
+// Adam moments, gradient and the transposed weight images (zeroed once).
+hbl_status prelu_opt_state(hbl_prelu_net* m) {
+    if (m->d_m) return HBL_OK;
+    const int64_t wp = m->im.wp, H = m->shape.hidden;
+    HBL_HIP(hipMalloc((void**)&m->d_m, sizeof(float) * m->nparams));
+    HBL_HIP(hipMalloc((void**)&m->d_v, sizeof(float) * m->nparams));
+    HBL_HIP(hipMalloc((void**)&m->d_grad, sizeof(float) * m->nparams));
+    if (H > 1) {
+        HBL_HIP(hipMalloc((void**)&m->d_wt, sizeof(uint16_t) * (H - 1) * wp * wp));
+        HBL_HIP(hipMemset(m->d_wt, 0, sizeof(uint16_t) * (H - 1) * wp * wp));
+    }
+    HBL_HIP(hipMemset(m->d_m, 0, sizeof(float) * m->nparams));
+    HBL_HIP(hipMemset(m->d_v, 0, sizeof(float) * m->nparams));
+    return HBL_OK;
+}
+
 // Training buffers for batches of B samples (grow-only in the padded size).
 hbl_status prelu_train_buffers(hbl_prelu_net* m, int32_t B, int64_t loss_slots, hipStream_t s) {
     const int tile = dense_tile_rows();
     const int32_t bp = (B + tile - 1) / tile * tile;
     const int64_t wp = m->im.wp, H = m->shape.hidden;
     const int32_t np = (int32_t)((wp + 1 + tile - 1) / tile * tile);
-    if (!m->d_m) {
-        HBL_HIP(hipMalloc((void**)&m->d_m, sizeof(float) * m->nparams));
-        HBL_HIP(hipMalloc((void**)&m->d_v, sizeof(float) * m->nparams));
-        HBL_HIP(hipMalloc((void**)&m->d_grad, sizeof(float) * m->nparams));
-        if (H > 1) HBL_HIP(hipMalloc((void**)&m->d_wt, sizeof(uint16_t) * (H - 1) * wp * wp));
-        HBL_HIP(hipMemset(m->d_m, 0, sizeof(float) * m->nparams));
-        HBL_HIP(hipMemset(m->d_v, 0, sizeof(float) * m->nparams));
-    }
+    if (hbl_status st = prelu_opt_state(m)) return st;
     if (loss_slots > m->loss_slots) {
         if (m->d_loss) { HBL_HIP(hipStreamSynchronize(s)); (void)hipFree(m->d_loss); m->d_loss = nullptr; }
         HBL_HIP(hipMalloc((void**)&m->d_loss, sizeof(double) * loss_slots));
@@ -1737,6 +1746,119 @@ hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zo
     }
     if (d_test) (void)hipFree(d_test);
     return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- wide PReLU model file
+namespace {
+
+constexpr uint64_t kPreluMagic = 0x31504C42484C4248ull;  // "HBLHBLP1"
+
+struct PreluFileHeader {
+    uint64_t magic;
+    int32_t shape[4];
+    int32_t has_norm, has_stage, has_moments, pad;
+    int64_t step, nparams;
+    double norm[24];
+    double dE_MeV, L, gamma_in;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t nbytes) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t q = 0; q < nbytes; ++q) { h ^= c[q]; h *= 1099511628211ull; }
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbl_status hbl_prelu_save(const hbl_prelu_net* m, const char* path) {
+    clear_error();
+    HBL_REQUIRE(m && path, "prelu_save: NULL argument");
+    const size_t np = (size_t)m->nparams;
+    const bool mom = m->d_m != nullptr;
+    std::vector<float> blob((mom ? 3 : 1) * np);
+    HBL_HIP(hipDeviceSynchronize());
+    HBL_HIP(hipMemcpy(blob.data(), m->d_params, sizeof(float) * np, hipMemcpyDeviceToHost));
+    if (mom) {
+        HBL_HIP(hipMemcpy(blob.data() + np, m->d_m, sizeof(float) * np, hipMemcpyDeviceToHost));
+        HBL_HIP(hipMemcpy(blob.data() + 2 * np, m->d_v, sizeof(float) * np, hipMemcpyDeviceToHost));
+    }
+    PreluFileHeader hdr;
+    memset(&hdr, 0, sizeof hdr);
+    hdr.magic = kPreluMagic;
+    hdr.shape[0] = m->shape.n_in; hdr.shape[1] = m->shape.width; hdr.shape[2] = m->shape.hidden; hdr.shape[3] = m->shape.n_out;
+    hdr.has_norm = m->has_norm;
+    hdr.has_stage = m->has_stage;
+    hdr.has_moments = mom;
+    hdr.step = m->step;
+    hdr.nparams = m->nparams;
+    memcpy(hdr.norm, m->norm, sizeof hdr.norm);
+    hdr.dE_MeV = m->dE_MeV; hdr.L = m->L; hdr.gamma_in = m->gamma_in;
+    uint64_t h = fnv1a(1469598103934665603ull, &hdr, sizeof hdr);
+    h = fnv1a(h, blob.data(), blob.size() * sizeof(float));
+    FILE* f = fopen(path, "wb");
+    if (!f) { set_error(HBL_EIO, "prelu_save: cannot open %s", path); return HBL_EIO; }
+    bool ok = fwrite(&hdr, sizeof hdr, 1, f) == 1 && fwrite(blob.data(), sizeof(float), blob.size(), f) == blob.size() &&
+              fwrite(&h, sizeof h, 1, f) == 1;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) { set_error(HBL_EIO, "prelu_save: write failed for %s", path); return HBL_EIO; }
+    return HBL_OK;
+}
+
+hbl_status hbl_prelu_load(const char* path, hbl_prelu_net** out) {
+    clear_error();
+    HBL_REQUIRE(path && out, "prelu_load: NULL argument");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) { set_error(HBL_EIO, "prelu_load: cannot open %s", path); return HBL_EIO; }
+    PreluFileHeader hdr;
+    bool ok = fread(&hdr, sizeof hdr, 1, f) == 1;
+    if (!ok || hdr.magic != kPreluMagic) {
+        fclose(f);
+        set_error(HBL_EIO, "prelu_load: %s is not a PReLU network file", path);
+        return HBL_EIO;
+    }
+    hbl_mlp_shape sh = {hdr.shape[0], hdr.shape[1], hdr.shape[2], hdr.shape[3]};
+    if (check_prelu_shape(&sh) != HBL_OK || hdr.nparams != prelu_nparams_of(&sh) || hdr.has_moments < 0 ||
+        hdr.has_moments > 1) {
+        fclose(f);
+        set_error(HBL_EIO, "prelu_load: %s has an inconsistent header", path);
+        return HBL_EIO;
+    }
+    const size_t np = (size_t)hdr.nparams;
+    std::vector<float> blob((hdr.has_moments ? 3 : 1) * np);
+    uint64_t stored = 0;
+    ok = fread(blob.data(), sizeof(float), blob.size(), f) == blob.size() && fread(&stored, sizeof stored, 1, f) == 1;
+    fclose(f);
+    if (!ok) { set_error(HBL_EIO, "prelu_load: %s is truncated", path); return HBL_EIO; }
+    uint64_t h = fnv1a(1469598103934665603ull, &hdr, sizeof hdr);
+    h = fnv1a(h, blob.data(), blob.size() * sizeof(float));
+    if (h != stored) { set_error(HBL_EIO, "prelu_load: checksum mismatch in %s", path); return HBL_EIO; }
+    hbl_prelu_net* m = nullptr;
+    if (hbl_status st = hbl_prelu_create(&sh, 0, &m)) return st;
+    hipError_t e = hipMemcpy(m->d_params, blob.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_dense_pack(m->d_params, DenseShape{sh.width, sh.hidden}, m->im, nullptr);
+    if (e == hipSuccess && hdr.has_moments) {
+        if (prelu_opt_state(m) != HBL_OK) e = hipErrorOutOfMemory;
+        if (e == hipSuccess) e = hipMemcpy(m->d_m, blob.data() + np, sizeof(float) * np, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->d_v, blob.data() + 2 * np, sizeof(float) * np, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        prelu_free(m);
+        set_error(HBL_EHIP, "prelu_load: upload failed: %s", hipGetErrorString(e));
+        return HBL_EHIP;
+    }
+    m->has_norm = hdr.has_norm != 0;
+    memcpy(m->norm, hdr.norm, sizeof m->norm);
+    m->has_stage = hdr.has_stage != 0;
+    m->dE_MeV = hdr.dE_MeV; m->L = hdr.L; m->gamma_in = hdr.gamma_in;
+    m->step = hdr.step;
+    *out = m;
+    return HBL_OK;
 }
 
 }  // extern "C"

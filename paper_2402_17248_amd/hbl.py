@@ -108,6 +108,8 @@ def _load():
         "hbl_prelu_apply_gaps": ([vp, i64, i64, vp, vp, vp, C.POINTER(Ref), vp], st),
         "hbl_prelu_loss_grad": ([vp, vp, vp, i64, C.POINTER(C.c_int32), i32, C.POINTER(C.c_float), dp, vp], st),
         "hbl_prelu_train": ([vp, vp, vp, i64, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp], st),
+        "hbl_prelu_save": ([vp, C.c_char_p], st),
+        "hbl_prelu_load": ([C.c_char_p, C.POINTER(vp)], st),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -348,14 +350,28 @@ class PreluNet:
     """The paper-shaped stage surrogate owned by libhbl: H hidden layers of
     width W with PReLU (one learned slope each), e.g. 3 x 700 or 5 x 900."""
 
-    def __init__(self, width: int, hidden: int, seed: int = 0):
-        h = C.c_void_p()
-        _call("hbl_prelu_create", C.byref(MlpShape(6, width, hidden, 6)), seed, C.byref(h))
-        self._h = h
+    def __init__(self, width: int, hidden: int, seed: int = 0, _handle=None):
+        if _handle is None:
+            h = C.c_void_p()
+            _call("hbl_prelu_create", C.byref(MlpShape(6, width, hidden, 6)), seed, C.byref(h))
+            _handle = h
+        self._h = _handle
         self.width, self.hidden = width, hidden
         n = C.c_int64()
         _call("hbl_prelu_num_params", self._h, C.byref(n))
         self.n_params = n.value
+
+    @staticmethod
+    def load(path: str) -> "PreluNet":
+        import struct
+        h = C.c_void_p()
+        _call("hbl_prelu_load", path.encode(), C.byref(h))
+        with open(path, "rb") as f:             # shape from the file header (after the 8-byte tag)
+            _, width, hidden, _ = struct.unpack("<4i", f.read(24)[8:24])
+        return PreluNet(width, hidden, _handle=h)
+
+    def save(self, path: str):
+        _call("hbl_prelu_save", self._h, path.encode())
 
     def flops_per_particle(self) -> int:
         """Multiply-adds x 2 of one forward pass (the network as defined, unpadded)."""

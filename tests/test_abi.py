@@ -154,3 +154,12 @@ def test_prelu_calls_reject_null_handles(hbl):
     assert hbl.lib.hbl_prelu_apply(BAD, 10, 10, None, None, None) == hbl.HBL_EINVAL
     assert hbl.lib.hbl_prelu_apply(BAD, 10, 9, None, None, None) == hbl.HBL_EINVAL
     assert hbl.lib.hbl_prelu_set_norm(None, (C.c_double * 24)()) == hbl.HBL_EINVAL
+
+
+def test_prelu_load_rejects_missing_and_foreign_files(hbl, tmp_path):
+    h = C.c_void_p()
+    assert hbl.lib.hbl_prelu_load(str(tmp_path / "none.bin").encode(), C.byref(h)) == hbl.HBL_EIO
+    p = tmp_path / "junk.bin"
+    p.write_bytes(b"not a network file" * 20)
+    assert hbl.lib.hbl_prelu_load(str(p).encode(), C.byref(h)) == hbl.HBL_EIO
+    assert "not a PReLU network file" in hbl.lib.hbl_last_error().decode()

@@ -143,3 +143,28 @@ def test_training_matches_oracle_loop(hbl, orc, pairs):
     assert log[-1, 1] < 0.7 * log[0, 1]
     assert np.all(np.abs(log / olog - 1) < 0.1), (log, olog)
     assert np.linalg.norm(pg - p) < 0.25 * moved
+
+
+def test_save_load_roundtrip(hbl, orc, pairs, tmp_path):
+    n, rec, out, xin, xout = pairs
+    net = hbl.PreluNet(72, 2, 4)
+    net.train(rec, out, n, batch=500, epochs=1, lr=1e-3, shuffle_seed=2)
+    wl = W.c3_stage(n=8)
+    entry = hbl.Ref.from_energy(wl.E_MeV)
+    net.set_stage(wl.beamline[1], entry)
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    back = hbl.PreluNet.load(path)
+    assert (back.width, back.hidden) == (72, 2)
+    assert np.array_equal(back.get_params(), net.get_params())
+    assert back.get_norm() == net.get_norm()
+    z1, z2 = rec[:, :1000].clone(), rec[:, :1000].clone()
+    r1, r2 = entry.copy(), entry.copy()
+    net.apply(z1, r1, n=1000)
+    back.apply(z2, r2, n=1000)
+    assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy()) and r1.gamma == r2.gamma
+    raw = bytearray(open(path, "rb").read())
+    raw[200] ^= 1
+    open(path, "wb").write(bytes(raw))
+    with pytest.raises(hbl.HblError):
+        hbl.PreluNet.load(path)
