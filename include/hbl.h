@@ -304,6 +304,11 @@ hbl_status hbl_prelu_num_params(const hbl_prelu_net* m, int64_t* n);
 /* SYNC.  Copy the FP32 parameters to / from host memory (n floats, finite). */
 hbl_status hbl_prelu_get_params(const hbl_prelu_net* m, float* host, int64_t n);
 hbl_status hbl_prelu_set_params(hbl_prelu_net* m, const float* host, int64_t n);
+/* SYNC.  Particles per inference chunk (default 65536; a multiple of 256 in
+ * [256, 2^22]): the two activation buffers hold chunk x W' bf16 each.
+ * Smaller chunks keep the activations in the last-level cache; larger ones
+ * give each layer launch more workgroups.  HBL_ENOMEM leaves the old ones. */
+hbl_status hbl_prelu_set_chunk(hbl_prelu_net* m, int64_t particles);
 /* norm24 as for hbl_surrogate_set_norm (host FP64, sd > 0). */
 hbl_status hbl_prelu_set_norm(hbl_prelu_net* m, const double norm24[24]);
 hbl_status hbl_prelu_get_norm(const hbl_prelu_net* m, double norm24[24]);

@@ -1399,6 +1399,32 @@ hbl_status hbl_prelu_set_params(hbl_prelu_net* m, const float* host, int64_t n) 
     return HBL_OK;
 }
 
+hbl_status hbl_prelu_set_chunk(hbl_prelu_net* m, int64_t particles) {
+    clear_error();
+    HBL_REQUIRE(m, "prelu_set_chunk: NULL network");
+    const int64_t tile = dense_tile_rows();
+    HBL_REQUIRE(particles >= tile && particles <= (int64_t)1 << 22 && particles % tile == 0,
+                "prelu_set_chunk: %lld particles must be a multiple of %lld in [%lld, 2^22]", (long long)particles,
+                (long long)tile, (long long)tile);
+    if (particles == m->chunk) return HBL_OK;
+    HBL_HIP(hipDeviceSynchronize());
+    const size_t bytes = sizeof(uint16_t) * (size_t)particles * m->im.wp;
+    uint16_t* b[2] = {nullptr, nullptr};
+    hipError_t e = hipMalloc((void**)&b[0], bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&b[1], bytes);
+    if (e != hipSuccess) {
+        if (b[0]) (void)hipFree(b[0]);
+        set_error(HBL_ENOMEM, "prelu_set_chunk: device allocation failed");
+        return HBL_ENOMEM;
+    }
+    (void)hipFree(m->d_buf[0]);
+    (void)hipFree(m->d_buf[1]);
+    m->d_buf[0] = b[0];
+    m->d_buf[1] = b[1];
+    m->chunk = particles;
+    return HBL_OK;
+}
+
 hbl_status hbl_prelu_set_norm(hbl_prelu_net* m, const double norm24[24]) {
     clear_error();
     HBL_REQUIRE(m && norm24, "prelu_set_norm: NULL argument");

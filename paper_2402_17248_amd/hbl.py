@@ -109,6 +109,7 @@ def _load():
         "hbl_prelu_loss_grad": ([vp, vp, vp, i64, C.POINTER(C.c_int32), i32, C.POINTER(C.c_float), dp, vp], st),
         "hbl_prelu_train": ([vp, vp, vp, i64, i64, C.POINTER(TrainCfg), C.POINTER(C.c_float), vp], st),
         "hbl_prelu_save": ([vp, C.c_char_p], st),
+        "hbl_prelu_set_chunk": ([vp, i64], st),
         "hbl_prelu_load": ([C.c_char_p, C.POINTER(vp)], st),
     }
     for name, (args, res) in sigs.items():
@@ -388,6 +389,9 @@ class PreluNet:
         import numpy as np
         p = np.ascontiguousarray(p, dtype=np.float32)
         _call("hbl_prelu_set_params", self._h, p.ctypes.data_as(C.POINTER(C.c_float)), len(p))
+
+    def set_chunk(self, particles: int):
+        _call("hbl_prelu_set_chunk", self._h, particles)
 
     def get_norm(self):
         out = (C.c_double * 24)()

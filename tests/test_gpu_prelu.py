@@ -169,3 +169,20 @@ def test_forward_parity_other_widths(hbl, orc, width, hidden):
     mx, med, frac = compare(g, c, norm)
     print(f"{width}x{hidden}: max {mx:.3e} median {med:.3e}")
     assert mx < 5e-3 and med < 1e-6 and frac < 0.01
+
+
+def test_chunk_size_does_not_change_results(hbl, orc):
+    """Chunking only splits the particles: any chunk gives the same bits."""
+    m = 5000
+    x, norm = bunch(orc, m, 25)
+    net = hbl.PreluNet(136, 3, 7)
+    net.set_norm(norm)
+    outs = []
+    for ch in (65536, 256, 1024):
+        net.set_chunk(ch)
+        z = to_dev(x)
+        net.apply(z, n=m)
+        outs.append(to_host(z, m))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    with pytest.raises(hbl.HblError):
+        net.set_chunk(1000)
