@@ -457,7 +457,7 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
     if (n > 0 && lat->n_elem > 0) {
         hipStream_t s = (hipStream_t)stream;
         if (flags == HBL_FUSED) {
-            HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_gen, lat->n_elem, lat->chromatic, s));
+            HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_gen, lat->d_kinds, lat->n_elem, lat->chromatic, s));
         } else if (lat->chromatic) {   // one launch per element, through its unified record
             for (int32_t i = 0; i < lat->n_elem; ++i)
                 HBL_HIP(launch_lattice_gen(z, n, ld, lat->d_gen + (size_t)kGen * i, true, s));

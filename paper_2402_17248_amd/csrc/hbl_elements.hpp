@@ -70,8 +70,18 @@ struct LatticeView {
     int32_t chromatic;    // any element chromatic
 };
 
+// A drift through its unified record's three nonzero off-diagonal terms
+// (g1 = g7 = L, g12 = L/(beta gamma)^2): the specialised drift map, bitwise.
+__device__ __forceinline__ void el_drift_gen(P6& p, const double* g) {
+    p.x = fma(g[1], p.px, p.x);
+    p.y = fma(g[7], p.py, p.y);
+    p.t = fma(g[12], p.pt, p.t);
+}
+
 // Apply the sequence to one particle: the unified record of each element,
-// read by scalar loads (uniform across the wavefront), no branches.
+// read by scalar loads (uniform across the wavefront), no branches (inside
+// the register-heavy stage and inference kernels a drift branch measured
+// slower: its register copies cost more than the FMAs it saves).
 template <bool CHROM = false>
 __device__ __forceinline__ void apply_elements(P6& p, const LatticeView& lv) {
     for (int32_t e = 0; e < lv.n; ++e) el_unified<CHROM>(p, lv.gen + (int64_t)e * kGen);

@@ -72,8 +72,8 @@ struct StageParams {
 hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
                                 const double* mean, const double* sigma, int64_t i0,
                                 hipStream_t s);
-hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, int32_t n_elem,
-                                bool chromatic, hipStream_t s);
+hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, const int32_t* kinds,
+                                int32_t n_elem, bool chromatic, hipStream_t s);
 // One element through its unified record (unfused push of a chromatic lattice).
 hipError_t launch_lattice_gen(double* z, int64_t n, int64_t ld, const double* gen1, bool chromatic,
                               hipStream_t s);

@@ -101,17 +101,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z
 
 // --------------------------------------------------------------- lattice
 // Fused lattice: each thread keeps kPer particles in registers through the
-// whole element sequence, every element applied through its unified record
-// (branch-free; coefficients are wavefront-uniform scalar loads).  One tile
+// whole element sequence; drifts (the most common element) take their 3-FMA
+// map, every other element its unified record (coefficients and kinds are
+// wavefront-uniform scalar loads, the drift test a scalar branch).  One tile
 // of kPer*kBlock particles per block (grid-stride beyond 2^20 blocks): a
-// persistent, capped grid measured 20 % slower, and the switch over element
-// kinds cost more in register copies than the unified form's extra FMAs.
+// persistent, capped grid measured 20 % slower, and a switch over all the
+// element kinds cost more in register copies than the FMAs it saves.
 constexpr int kPer = 2;
 
 template <bool CHROM>
 __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z, int64_t n,
                                                           int64_t ld, const double* __restrict__ gen,
-                                                          int32_t n_elem) {
+                                                          const int32_t* __restrict__ kinds, int32_t n_elem) {
     const int64_t tile = (int64_t)kPer * kBlock;
     for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile) {
         P6 p[kPer];
@@ -126,8 +127,13 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
 #pragma unroll 2
         for (int32_t e = 0; e < n_elem; ++e) {
             const double* g = gen + (int64_t)e * kGen;
+            if (kinds[e] == kDrift) {
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) el_unified<CHROM>(p[k], g);
+                for (int k = 0; k < kPer; ++k) el_drift_gen(p[k], g);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) el_unified<CHROM>(p[k], g);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
@@ -290,14 +296,14 @@ hipError_t launch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t seed,
     return hipGetLastError();
 }
 
-hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, int32_t n_elem,
-                                bool chromatic, hipStream_t s) {
+hipError_t launch_lattice_fused(double* z, int64_t n, int64_t ld, const double* gen, const int32_t* kinds,
+                                int32_t n_elem, bool chromatic, hipStream_t s) {
     if (n == 0 || n_elem == 0) return hipSuccess;
     const int grid = grid_for(n, (int64_t)kPer * kBlock, 1 << 20);
     if (chromatic)
-        hipLaunchKernelGGL(k_lattice_fused<true>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, n_elem);
+        hipLaunchKernelGGL(k_lattice_fused<true>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, kinds, n_elem);
     else
-        hipLaunchKernelGGL(k_lattice_fused<false>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, n_elem);
+        hipLaunchKernelGGL(k_lattice_fused<false>, dim3(grid), dim3(kBlock), 0, s, z, n, ld, gen, kinds, n_elem);
     return hipGetLastError();
 }
 
