@@ -78,6 +78,17 @@ __device__ __forceinline__ void el_drift_gen(P6& p, const double* g) {
     p.t = fma(g[12], p.pt, p.t);
 }
 
+// A thick quadrupole through its unified record's nonzero terms (the two
+// plane matrices and the t-pt term): the specialised quad map, bitwise.
+__device__ __forceinline__ void el_quad_gen(P6& p, const double* g) {
+    const double x = p.x, px = p.px, y = p.y, py = p.py;
+    p.x = fma(g[1], px, g[0] * x);
+    p.px = fma(g[4], px, g[3] * x);
+    p.y = fma(g[7], py, g[6] * y);
+    p.py = fma(g[9], py, g[8] * y);
+    p.t = fma(g[12], p.pt, p.t);
+}
+
 // Apply the sequence to one particle: the unified record of each element,
 // read by scalar loads (uniform across the wavefront), no branches (inside
 // the register-heavy stage and inference kernels a drift branch measured

@@ -127,9 +127,13 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
 #pragma unroll 2
         for (int32_t e = 0; e < n_elem; ++e) {
             const double* g = gen + (int64_t)e * kGen;
-            if (kinds[e] == kDrift) {
+            const int32_t kind = kinds[e];
+            if (kind == kDrift) {
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) el_drift_gen(p[k], g);
+            } else if (!CHROM && kind == kQuad) {
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) el_quad_gen(p[k], g);
             } else {
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) el_unified<CHROM>(p[k], g);
