@@ -107,6 +107,26 @@ __device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, 
     p.pt = z[5 * ld + i];
 }
 
+// Streaming variants (non-temporal hint): the fused lattice reads and writes
+// each particle exactly once.
+__device__ __forceinline__ void load6_nt(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {
+    p.x = __builtin_nontemporal_load(z + i);
+    p.y = __builtin_nontemporal_load(z + ld + i);
+    p.t = __builtin_nontemporal_load(z + 2 * ld + i);
+    p.px = __builtin_nontemporal_load(z + 3 * ld + i);
+    p.py = __builtin_nontemporal_load(z + 4 * ld + i);
+    p.pt = __builtin_nontemporal_load(z + 5 * ld + i);
+}
+
+__device__ __forceinline__ void store6_nt(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
+    __builtin_nontemporal_store(p.x, z + i);
+    __builtin_nontemporal_store(p.y, z + ld + i);
+    __builtin_nontemporal_store(p.t, z + 2 * ld + i);
+    __builtin_nontemporal_store(p.px, z + 3 * ld + i);
+    __builtin_nontemporal_store(p.py, z + 4 * ld + i);
+    __builtin_nontemporal_store(p.pt, z + 5 * ld + i);
+}
+
 __device__ __forceinline__ void store6(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
     z[i] = p.x;
     z[ld + i] = p.y;

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = base + k * kBlock + threadIdx.x;
             live[k] = i < n;
-            if (live[k]) load6(z, ld, i, p[k]);
+            if (live[k]) load6_nt(z, ld, i, p[k]);
             else p[k] = P6{0, 0, 0, 0, 0, 0};
         }
 #pragma unroll 2
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = base + k * kBlock + threadIdx.x;
-            if (live[k]) store6(z, ld, i, p[k]);
+            if (live[k]) store6_nt(z, ld, i, p[k]);
         }
     }
 }
