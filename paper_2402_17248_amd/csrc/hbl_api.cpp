@@ -1523,15 +1523,27 @@ uint16_t* const* prelu_wt(const hbl_prelu_net* m, uint16_t** wt) {
 hbl_status prelu_opt_state(hbl_prelu_net* m) {
     if (m->d_m) return HBL_OK;
     const int64_t wp = m->im.wp, H = m->shape.hidden;
-    HBL_HIP(hipMalloc((void**)&m->d_m, sizeof(float) * m->nparams));
-    HBL_HIP(hipMalloc((void**)&m->d_v, sizeof(float) * m->nparams));
-    HBL_HIP(hipMalloc((void**)&m->d_grad, sizeof(float) * m->nparams));
-    if (H > 1) {
-        HBL_HIP(hipMalloc((void**)&m->d_wt, sizeof(uint16_t) * (H - 1) * wp * wp));
-        HBL_HIP(hipMemset(m->d_wt, 0, sizeof(uint16_t) * (H - 1) * wp * wp));
+    const size_t pb = sizeof(float) * (size_t)m->nparams, wtb = sizeof(uint16_t) * (size_t)(H - 1) * wp * wp;
+    float *dm = nullptr, *dv = nullptr, *dg = nullptr;
+    uint16_t* wt = nullptr;
+    hipError_t e = hipMalloc((void**)&dm, pb);
+    if (e == hipSuccess) e = hipMalloc((void**)&dv, pb);
+    if (e == hipSuccess) e = hipMalloc((void**)&dg, pb);
+    if (e == hipSuccess && H > 1) e = hipMalloc((void**)&wt, wtb);
+    if (e == hipSuccess) e = hipMemset(dm, 0, pb);
+    if (e == hipSuccess) e = hipMemset(dv, 0, pb);
+    if (e == hipSuccess && wt) e = hipMemset(wt, 0, wtb);
+    if (e != hipSuccess) {                 // all or nothing: the handle stays as it was
+        void* ptrs[] = {dm, dv, dg, wt};
+        for (void* q : ptrs)
+            if (q) (void)hipFree(q);
+        set_error(HBL_ENOMEM, "prelu: optimiser state allocation failed: %s", hipGetErrorString(e));
+        return HBL_ENOMEM;
     }
-    HBL_HIP(hipMemset(m->d_m, 0, sizeof(float) * m->nparams));
-    HBL_HIP(hipMemset(m->d_v, 0, sizeof(float) * m->nparams));
+    m->d_m = dm;
+    m->d_v = dv;
+    m->d_grad = dg;
+    m->d_wt = wt;
     return HBL_OK;
 }
 
