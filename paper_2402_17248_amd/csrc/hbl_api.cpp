@@ -1560,8 +1560,13 @@ hbl_status prelu_train_buffers(hbl_prelu_net* m, int32_t B, int64_t loss_slots, 
         m->loss_slots = loss_slots;
     }
     if (bp > m->train_bp) {
+        // the old buffers go first; until the new ones are in place the
+        // handle has none (train_bp = 0), so a failure here cannot leave
+        // stale pointers behind
         if (m->d_train) { HBL_HIP(hipStreamSynchronize(s)); (void)hipFree(m->d_train); m->d_train = nullptr; }
         if (m->d_idx) { (void)hipFree(m->d_idx); m->d_idx = nullptr; }
+        m->train_bp = 0;
+        m->train_B = -1;
         size_t off = 0;
         auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
         DenseTrainBufs t{};
