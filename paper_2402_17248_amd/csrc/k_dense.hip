@@ -256,8 +256,9 @@ __global__ __launch_bounds__(256 * WM) __attribute__((amdgpu_waves_per_eu(WM, WM
         }
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
-            const int ar = mt * 16 + r;
-            o.a[mt] = *(const __attribute__((address_space(3))) bf16x8*)(A + ar * 64 + ((g ^ swz(ar)) * 16));
+            const int ar = mt * 16 + r;                 // row within this wave's rows; the
+            const int arow = wm * (MTW * 16) + ar;      // swizzle follows the M-block row
+            o.a[mt] = *(const __attribute__((address_space(3))) bf16x8*)(A + ar * 64 + ((g ^ swz(arow)) * 16));
         }
     };
     auto products = [&](const Ops& o) {
