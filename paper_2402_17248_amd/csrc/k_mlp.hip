@@ -81,8 +81,7 @@ __host__ __device__ __forceinline__ int perm_feature(int c, int g, int j) {
 //                   K slot 8g + j (j < 4) <-> output row 4g + j, others 0
 //   words 156..187  W2^T, (mt, c): 156 + 8mt + 4c, K slots permuted as above
 //   words 188..219  W1^T, (mt, c): 188 + 8mt + 4c
-constexpr int kImgWords = 220;
-constexpr int kImgFwdWords = 140;
+constexpr int kImgWords = 220;           // words 0..139 are the forward image
 
 // Flat FP32 parameter offsets (row-major [out][in] weights, then bias).
 constexpr int kOffW0 = 0, kOffB0 = 384, kOffW1 = 448, kOffB1 = 4544, kOffW2 = 4608,
