@@ -656,7 +656,7 @@ def main():
         print(json.dumps({"paper_shaped_surrogates": out}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; there is no multi-GPU path "
+        print(json.dumps({"error": "the library runs on one GPU only; there is no multi-GPU path "
                                    "(particles shard by index with no exchange but a 27-value "
                                    "moment merge; not built)", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
