@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
     ap.add_argument("--only-paper-shapes", action="store_true",
                     help="run only the paper-shaped PReLU surrogate studies (inference and training)")
+    ap.add_argument("--only-configs", action="store_true",
+                    help="run only the timing of the other configurations (FODO, 58-element "
+                         "lattice, 2000-substep stage)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-single-stage", action="store_true",
@@ -62,7 +65,8 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter passes: one plain device copy of 1 GiB "
                          "(calibration), then the benchmark's four surrogate passes (inference "
-                         "with the gaps fused, untrained weights) on the benchmark bunch, twice")
+                         "with the gaps fused, untrained weights) on the benchmark bunch, twice; "
+                         "with --only-configs the 58-element lattice push instead")
     return ap.parse_args()
 
 
@@ -80,6 +84,19 @@ def pmc_probe(args):
     b = torch.empty_like(a)
     b.copy_(a)                                                           # reads 1 GiB, writes 1 GiB
     torch.cuda.synchronize()
+    if args.only_configs:
+        # the 58-element fused lattice on the benchmark bunch size, twice
+        wl = W.c2_fused()
+        n = args.n
+        ref = hbl.Ref.from_energy(wl.E_MeV)
+        lat = hbl.Lattice(wl.beamline[0], ref)
+        z = hbl.new_bunch(n)
+        for _ in range(2):
+            hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+            lat.push(z, ref.copy(), n=n)
+        torch.cuda.synchronize()
+        log(f"pmc probe done: copy 1 GiB, 2 x {lat.n_elem}-element lattice push on {n} particles")
+        return
     wl = W.c5_chain(n=args.n)
     n = wl.bunch.n
     chain = Chain(wl.beamline, wl.E_MeV)
@@ -647,6 +664,11 @@ def main():
     args = parse()
     if args.pmc_probe:
         pmc_probe(args)
+        return
+    if args.only_configs:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"other_configs": config_studies(log)}), flush=True)
         return
     if args.only_paper_shapes:
         import torch
