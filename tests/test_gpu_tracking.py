@@ -107,6 +107,32 @@ def test_zero_particles_is_noop(hbl):
     assert abs(ref.gamma - 10000.0 / hbl.MEC2_MEV) < 1e-9
 
 
+def test_zero_particles_surrogates_and_moments(hbl):
+    """n = 0 through both surrogate kinds with gaps fused: the bunch is not
+    touched and the reference still crosses the gaps and the stage; the
+    moments of no particles are an argument error, raised before any launch."""
+    torch = __import__("torch")
+    z = hbl.new_bunch(8)
+    hbl.fill_gaussian(z, 3, (0.0,) * 6, sig(), n=8)
+    before = z.clone()
+    st = W.plasma_stage(nsub=10)
+    norm = [0.0] * 6 + list(sig()) + [0.0] * 6 + list(sig())
+    for net in (hbl.Surrogate(1), hbl.PreluNet(64, 2, seed=1)):
+        ref = hbl.Ref.from_energy(1000.0)
+        pre = hbl.Lattice(W.triplet(), ref)
+        net.set_norm(norm)
+        net.set_stage(st, ref)
+        post = hbl.Lattice(W.triplet(), hbl.Ref(hbl.MEC2_MEV, ref.gamma + st.dE_MeV / hbl.MEC2_MEV, 0.0))
+        net.apply(z, ref, n=0, pre=pre, post=post)
+        torch.cuda.synchronize()
+        assert torch.equal(z, before)
+        assert abs(ref.gamma - 10000.0 / hbl.MEC2_MEV) < 1e-9
+        assert abs(ref.s - (2 * pre.length + st.L)) < 1e-12
+    with pytest.raises(hbl.HblError) as ei:
+        hbl.moments(z, n=0)
+    assert ei.value.status == hbl.HBL_EINVAL
+
+
 @pytest.mark.parametrize("n", [1, 2001])
 def test_stage_parity_with_record(hbl, orc, n):
     wl = W.c3_stage(n=n)
