@@ -30,6 +30,11 @@
  *  - Handles (lattice, surrogate) own small device buffers on the device that
  *    was current when they were created; use them with that device current.
  *    A handle must not be used by two threads at once.
+ *  - The reductions (hbl_moments, hbl_moments_async, hbl_compare) share one
+ *    workspace per device, grown on demand and kept until the process ends:
+ *    reductions that could run at the same time (enqueued on different
+ *    streams, or from different threads) race on it, so keep them on one
+ *    stream.
  */
 #ifndef HBL_H
 #define HBL_H
