@@ -714,29 +714,38 @@ def main():
     n_pass = len(chain.passes())        # stage passes per step, one kernel launch each
 
     def step(use_sur, ev=None):
-        hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
         if ev is not None:
             ev[0].record()
-        chain.run(z, n=n, use_surrogates=use_sur)
+        hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, sig, n=n)
         if ev is not None:
             ev[1].record()
+        chain.run(z, n=n, use_surrogates=use_sur)
+        if ev is not None:
+            ev[2].record()
         hbl.moments_async(z, out27, n=n)
+        if ev is not None:
+            ev[3].record()
+
+    breakdown = {}
 
     def timed(use_sur, steps, warmup):
         """Wall time per step over exactly `steps` steps, and the average
         duration of one stage-pass launch from HIP events recorded on the
-        library's stream around the passes inside those same steps."""
+        library's stream around the passes inside those same steps (events
+        around the fill and the moments give the rest of the step)."""
         for _ in range(warmup):
             step(use_sur)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)]
+        evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4)) for _ in range(steps)]
         torch.cuda.synchronize()
         t = time.perf_counter()
         for k in range(steps):
             step(use_sur, evs[k])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        per_launch = sum(a.elapsed_time(b) for a, b in evs) * 1e-3 / steps / n_pass
+        part = [sum(e[j].elapsed_time(e[j + 1]) for e in evs) / steps for j in range(3)]
+        breakdown["surrogate" if use_sur else "fine_step"] = {
+            "fill_ms": part[0], "stage_passes_ms": part[1], "moments_ms": part[2]}
+        per_launch = part[1] * 1e-3 / n_pass
         return dt, per_launch
 
     def time_chain(c, steps, warmup):
@@ -758,7 +767,9 @@ def main():
         return (time.perf_counter() - t) / steps
 
     dt_sur, t_inf = timed(True, args.steps, args.warmup)
-    log(f"surrogate chain: {dt_sur * 1e3:.3f} ms/step, {n / dt_sur:.4g} particles/s")
+    log(f"surrogate chain: {dt_sur * 1e3:.3f} ms/step, {n / dt_sur:.4g} particles/s (HIP events: fill "
+        f"{breakdown['surrogate']['fill_ms']:.3f} ms, {n_pass} stage passes "
+        f"{breakdown['surrogate']['stage_passes_ms']:.3f} ms, moments {breakdown['surrogate']['moments_ms']:.3f} ms)")
     dt_fine, t_fs = timed(False, args.fine_steps, 1)
     log(f"fine-step chain: {dt_fine * 1e3:.3f} ms/step, {n / dt_fine:.4g} particles/s")
 
@@ -817,6 +828,7 @@ def main():
                            "speedup_surrogate": dt_fine / dt_sur},
         "accuracy_vs_fine_step": {"eps_rel_xyt": eps_rel, "rms_over_sigma": rms,
                                   "centroid_over_sigma": cen},
+        "step_breakdown_ms": breakdown,
         "stage_pass_kernels": {"inference_ms": t_inf * 1e3, "fine_step_ms": t_fs * 1e3,
                                "speedup": t_fs / t_inf, "launches_per_step": n_pass,
                                "dense_mfma_tflops": mfma_achieved,
