@@ -104,11 +104,22 @@ struct MomentsOp {
         double a[6], b[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            a[j] = z[j * ld + i];
-            b[j] = z[j * ld + k];
+            a[j] = __builtin_nontemporal_load(z + j * ld + i);
+            b[j] = __builtin_nontemporal_load(z + j * ld + k);
         }
         accumulate(a, acc);
         accumulate(b, acc);
+    }
+    // four particles i, i + st, i + 2 st, i + 3 st: all 24 loads in flight
+    // before the first feeds the accumulation (same order as one at a time)
+    __device__ __forceinline__ void add4(int64_t i, int64_t st, double (&acc)[NV]) const {
+        double a[4][6];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int j = 0; j < 6; ++j) a[r][j] = __builtin_nontemporal_load(z + j * ld + i + r * st);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accumulate(a[r], acc);
     }
     __device__ __forceinline__ void accumulate(const double (&v)[6], double (&acc)[NV]) const {
         double d[6];
@@ -127,7 +138,7 @@ struct MomentsOp {
     __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
         double d[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) d[j] = z[j * ld + i] - sh[j];
+        for (int j = 0; j < 6; ++j) d[j] = __builtin_nontemporal_load(z + j * ld + i) - sh[j];
 #pragma unroll
         for (int j = 0; j < 6; ++j) acc[j] += d[j];
 #pragma unroll
@@ -150,8 +161,8 @@ struct Diff2Op {
         double a[6], b[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            a[j] = zs[j * ld + i] - zf[j * ld + i];
-            b[j] = zs[j * ld + k] - zf[j * ld + k];
+            a[j] = __builtin_nontemporal_load(zs + j * ld + i) - __builtin_nontemporal_load(zf + j * ld + i);
+            b[j] = __builtin_nontemporal_load(zs + j * ld + k) - __builtin_nontemporal_load(zf + j * ld + k);
         }
 #pragma unroll
         for (int j = 0; j < 6; ++j) acc[j] = fma(a[j], a[j], acc[j]);
@@ -161,7 +172,7 @@ struct Diff2Op {
     __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            const double d = zs[j * ld + i] - zf[j * ld + i];
+            const double d = __builtin_nontemporal_load(zs + j * ld + i) - __builtin_nontemporal_load(zf + j * ld + i);
             acc[j] = fma(d, d, acc[j]);
         }
     }
@@ -177,8 +188,13 @@ __global__ __launch_bounds__(kBlock) void k_partials(Op op, int64_t n, DD* __res
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // two particles per iteration: both loads are in flight before either
-    // feeds the (fixed-order) accumulation
+    // several particles per iteration (four for the moments, two for the
+    // paired differences): their loads are in flight before the first feeds
+    // the (fixed-order) accumulation; the bunch is streamed once, so the loads
+    // are non-temporal.  Moments of 2.5e7 particles: 240 us with two plain
+    // loads per iteration, 218 us non-temporal, 197 us with four (6.1 TB/s).
+    if constexpr (NV == 27)
+        for (; i + 3 * stride < n; i += 4 * stride) op.add4(i, stride, acc);
     for (; i + stride < n; i += 2 * stride) {
         op.add2(i, i + stride, acc);
     }
