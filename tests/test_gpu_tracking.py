@@ -93,6 +93,26 @@ def test_lattice58_fused_equals_unfused_and_oracle(hbl, orc):
     assert rel_err(g[:, cols], c).max() < TOL
 
 
+def test_lattice58_full_size_sampled(hbl, orc):
+    """The 58-element fused lattice on 2.5e7 particles (the largest size the
+    benchmark times it at; 2.5e7 = 24,414 tiles of 1,024 + a 64-particle
+    tail), device-filled bunch, sampled particles (the last one included)
+    against the oracle's own fill and push."""
+    torch = __import__("torch")
+    wl = W.c2_fused()
+    n = 25_000_000
+    z = hbl.new_bunch(n)
+    hbl.fill_gaussian(z, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=n)
+    ref = hbl.Ref.from_energy(wl.E_MeV)
+    hbl.Lattice(wl.beamline[0], ref).push(z, ref, n=n)
+    idx = np.sort(np.random.default_rng(3).choice(n, 20_000, replace=False))
+    idx[-1] = n - 1
+    g = z[:, torch.from_numpy(idx).cuda()].cpu().numpy()
+    c = orc.fill_gaussian(0, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, idx=idx)
+    orc.push(c, wl.beamline[0], orc.Ref.from_energy(wl.E_MeV))
+    assert rel_err(g, c).max() < TOL
+
+
 def test_zero_particles_is_noop(hbl):
     z = hbl.new_bunch(4)
     before = z.clone()
