@@ -119,3 +119,30 @@ def test_moments_async_matches_sync(hbl):
     m, c = hbl.moments(z, n=n)
     torch.cuda.synchronize()
     assert out.cpu().tolist() == m + c
+
+
+def test_compare_full_size_constant_shift(hbl):
+    """Properties that hold at any size, checked at 2.5e7 particles (the
+    benchmark bunch; 95 particles per thread, so the four-at-a-time loop,
+    the pair loop and the single tail all run): a test bunch equal to the
+    reference shifted by a constant c_j per row has rms_j = |c_j|/sigma_j and
+    centroid_j = c_j/sigma_j (sigma of the reference), and unchanged
+    emittances."""
+    torch = __import__("torch")
+    n = 25_000_000
+    sig = W.BunchSpec(1, 1).sigma
+    zf = hbl.new_bunch(n)
+    hbl.fill_gaussian(zf, 21, (0.0,) * 6, sig, n=n)
+    shift = [0.25 * s for s in sig]
+    shift[1] = -shift[1]
+    zs = zf.clone()
+    zs[:, :n] += torch.tensor(shift, dtype=torch.float64, device="cuda")[:, None]
+    _, cov = hbl.moments(zf, n=n)
+    sd = [math.sqrt(cov[j * 6 - j * (j - 1) // 2]) for j in range(6)]   # diagonal of the upper triangle
+    r, c, e = hbl.compare(zs, zf, n=n)
+    for j in range(6):
+        # the shifted rows are rounded once (ulp of |z| ~ 4 sigma), so the
+        # differences are c_j to ~1e-15 relative of sigma
+        assert abs(r[j] - abs(shift[j]) / sd[j]) < 1e-12, (j, r[j])
+        assert abs(c[j] - shift[j] / sd[j]) < 1e-12, (j, c[j])
+    assert max(abs(x) for x in e) < 1e-12, e
