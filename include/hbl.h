@@ -23,7 +23,10 @@
  *    marked ASYNC only enqueue work on it; calls marked SYNC wait for it.
  *    Particle data never leaves the device (§2, §4.3).
  *  - Errors: every call returns an hbl_status; arguments are validated before
- *    any GPU work is enqueued, and a rejected call has no effect.
+ *    any GPU work is enqueued, and a rejected call has no effect.  Device
+ *    arguments must be memory of the current HIP device (hipMalloc'd or
+ *    managed) whose allocation holds every row they span; a host pointer,
+ *    memory of another device or a range past its allocation is HBL_EINVAL.
  *    hbl_last_error() gives a message for the calling thread's last failure.
  *    A device fault in enqueued work surfaces at the next SYNC call.  No C++
  *    exception crosses this interface.
@@ -151,6 +154,14 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
  * emits (input, output) training pairs (§3). */
 hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* stage,
                            hbl_ref* ref, double* record, int64_t record_ld, hbl_stream stream);
+
+/* Host only.  Newton steps per substep that hbl_apply_stage uses for the
+ * particle's 1/gamma_i at the given entry reference: the reciprocal of the
+ * previous substep has relative error at most d = |gamma ramp per substep| /
+ * (0.9 min(gamma_in, gamma_out)) (twice that for a chirped stage), k steps
+ * leave d^(2^k), and the fewest k in 1..4 with d^(2^k) < 1e-17 is taken;
+ * *steps = 0 means every substep divides.  Validates like hbl_apply_stage. */
+hbl_status hbl_stage_newton_steps(const hbl_element* stage, const hbl_ref* ref, int32_t* steps);
 
 /* ASYNC.  One pass over the bunch equivalent to hbl_push_lattice(pre),
  * hbl_apply_stage(stage), hbl_push_lattice(post): the transport gaps before

@@ -153,6 +153,51 @@ hbl_status check_bunch(const void* z, int64_t n, int64_t ld, const char* what) {
     return HBL_OK;
 }
 
+// `bytes` bytes from p must lie in one HIP allocation of the current device:
+// a host pointer, memory of another device or a range past the allocation
+// would fault the kernel or corrupt a neighbour.  Called after the other
+// checks, just before work is enqueued (a failed query's HIP error is
+// cleared, so it cannot surface at a later launch).
+hbl_status check_device(const void* p, size_t bytes, const char* what) {
+    if (bytes == 0) return HBL_OK;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(HBL_EHIP, "%s: no current HIP device", what);
+        return HBL_EHIP;
+    }
+    hipPointerAttribute_t a;
+    memset(&a, 0, sizeof a);
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(HBL_EINVAL, "%s: %p is not HIP device memory", what, p);
+        return HBL_EINVAL;
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) {
+        set_error(HBL_EINVAL, "%s: %p is host memory, not device memory", what, p);
+        return HBL_EINVAL;
+    }
+    if (a.device != dev) {
+        set_error(HBL_EINVAL, "%s: memory of device %d used with device %d current", what, a.device, dev);
+        return HBL_EINVAL;
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(HBL_EINVAL, "%s: no allocation holds %p", what, p);
+        return HBL_EINVAL;
+    }
+    if ((uintptr_t)p + bytes > (uintptr_t)base + size) {
+        set_error(HBL_EINVAL, "%s: %zu bytes from %p run past the end of their allocation", what, bytes, p);
+        return HBL_EINVAL;
+    }
+    return HBL_OK;
+}
+
+// Bytes spanned by the six rows of a bunch of n particles, leading dimension ld.
+size_t bunch_bytes(int64_t n, int64_t ld) { return n > 0 ? (size_t)(5 * ld + n) * sizeof(double) : 0; }
+
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 hbl_status check_ref(const hbl_ref* ref) {
@@ -350,6 +395,7 @@ hbl_status hbl_bunch_fill_gaussian(double* z, int64_t n, int64_t ld, uint64_t se
                     "fill_gaussian: mean/sigma[%d] must be finite, sigma >= 0", j);
     HBL_REQUIRE(i0 >= 0 && i0 <= INT64_MAX - n, "fill_gaussian: bad first index");
     if (n == 0) return HBL_OK;
+    if (hbl_status st = check_device(z, bunch_bytes(n, ld), "fill_gaussian")) return st;
     HBL_HIP(launch_fill_gaussian(z, n, ld, seed, mean, sigma, i0, (hipStream_t)stream));
     return HBL_OK;
 }
@@ -455,6 +501,7 @@ hbl_status hbl_push_lattice(double* z, int64_t n, int64_t ld, const hbl_lattice*
                 ref->gamma);
     HBL_REQUIRE(flags == HBL_FUSED || flags == HBL_UNFUSED, "push_lattice: unknown flags 0x%x", flags);
     if (n > 0 && lat->n_elem > 0) {
+        if (hbl_status st = check_device(z, bunch_bytes(n, ld), "push_lattice")) return st;
         hipStream_t s = (hipStream_t)stream;
         if (flags == HBL_FUSED) {
             HBL_HIP(launch_lattice_fused(z, n, ld, lat->d_gen, lat->d_kinds, lat->n_elem, lat->chromatic, s));
@@ -492,6 +539,28 @@ hbl_status check_gap(const hbl_lattice* lat, double gamma, const char* what) {
     HBL_REQUIRE(lat->gamma == gamma, "%s lattice compiled for gamma %.17g, applied at gamma %.17g", what,
                 lat->gamma, gamma);
     return HBL_OK;
+}
+
+// Largest relative change of a particle's gamma over one substep: the ramp
+// gp h over the smallest gamma, particle energy offsets allowed down to 90 % of
+// the reference (a linear-optics beam stays far inside); doubled for a chirped
+// stage, whose particle ramp rate gp (1 + chirp t) is sized for |chirp t| <= 1.
+double reciprocal_drift(double g_in, double g_out, double gp, double h, double chirp) {
+    const double gmin = fmin(g_in, g_out) * 0.9;
+    return fabs(gp * h) * (chirp != 0.0 ? 2.0 : 1.0) / gmin;
+}
+
+// Newton steps r <- r (2 - a r) that take the previous substep's reciprocal,
+// relative error at most d, to 1/gamma_i: k steps leave d^(2^k); the fewest k
+// in 1..4 with d^(2^k) < 1e-17, else 0 (divide every substep).
+int32_t newton_steps(double d) {
+    if (!(d < 0.25)) return 0;
+    double err = d;
+    for (int32_t k = 1; k <= 4; ++k) {
+        err *= err;
+        if (err < 1e-17) return k;
+    }
+    return 0;
 }
 
 hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice* pre, const hbl_element* stage,
@@ -539,29 +608,14 @@ hbl_status apply_stage_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
     p.chirp_t = stage->chirp * (gp * L * L / (2.0 * g_in * g_out * g_out));
     p.inv_bgout = 1.0 / bg_out;
     p.nsub = N;
-    // Newton steps for 1/gamma_i from the previous substep: the relative
-    // change per substep is at most d = |gp h| / gamma_min, with particle
-    // energy offsets |dgamma_i| up to 10% of the reference (a linear-optics
-    // beam stays far inside); k steps reduce it to d^(2^k); require < 1e-17,
-    // else divide every substep.
-    // With a chirp the particle's ramp rate is gp (1 + chirp t): sized here for
-    // |chirp t| <= 1; the kernel divides for a particle beyond that.
-    const double gmin = fmin(g_in, g_out) * 0.9;
-    const double d = fabs(gp * h) * (stage->chirp != 0.0 ? 2.0 : 1.0) / gmin;
-    int newton = 0;
-    if (d < 0.25) {
-        double err = d;
-        newton = 1;
-        while (newton < 4) {
-            err = err * err;
-            if (err < 1e-17) break;
-            ++newton;
-        }
-        if (err >= 1e-17) newton = 0;
-    }
-    p.newton = newton;
+    // 1/gamma_i by Newton steps from the previous substep's reciprocal (a
+    // chirped particle beyond |chirp t| <= 1 divides in the kernel)
+    p.newton = newton_steps(reciprocal_drift(g_in, g_out, gp, h, stage->chirp));
     hbl_status st = HBL_OK;
     if (n > 0) {
+        if (hbl_status s2 = check_device(z, bunch_bytes(n, ld), "apply_stage")) return s2;
+        if (record)
+            if (hbl_status s2 = check_device(record, bunch_bytes(n, record_ld), "apply_stage record")) return s2;
         const double* tab = stage_table(g_in, gp, h, N, &st);
         if (!tab) return st;
         HBL_HIP(launch_stage(z, n, ld, record, record_ld, p, tab, view_of(pre), view_of(post),
@@ -581,6 +635,22 @@ hbl_status hbl_apply_stage(double* z, int64_t n, int64_t ld, const hbl_element* 
     return apply_stage_impl(z, n, ld, nullptr, stage, nullptr, ref, record, record_ld, stream);
 }
 
+hbl_status hbl_stage_newton_steps(const hbl_element* stage, const hbl_ref* ref, int32_t* steps) {
+    clear_error();
+    HBL_REQUIRE(stage && steps, "stage_newton_steps: NULL argument");
+    HBL_REQUIRE(stage->kind == HBL_STAGE, "stage_newton_steps: element kind %d is not a stage", (int)stage->kind);
+    HBL_REQUIRE(stage->nsub >= 1 && stage->nsub <= (1 << 24), "stage_newton_steps: nsub = %d out of [1, 2^24]",
+                (int)stage->nsub);
+    HBL_REQUIRE(finite_pos(stage->L), "stage_newton_steps: L must be finite and > 0");
+    HBL_REQUIRE(isfinite(stage->dE_MeV) && isfinite(stage->chirp), "stage_newton_steps: dE and chirp must be finite");
+    if (hbl_status st = check_ref(ref)) return st;
+    const double g_in = ref->gamma, g_out = g_in + stage->dE_MeV / ref->mass_MeV;
+    HBL_REQUIRE(g_out > 1.0 + 1e-6, "stage_newton_steps: exit gamma %g must exceed 1", g_out);
+    const double h = stage->L / stage->nsub, gp = (g_out - g_in) / stage->L;
+    *steps = newton_steps(reciprocal_drift(g_in, g_out, gp, h, stage->chirp));
+    return HBL_OK;
+}
+
 hbl_status hbl_apply_stage_gaps(double* z, int64_t n, int64_t ld, const hbl_lattice* pre,
                                 const hbl_element* stage, const hbl_lattice* post, hbl_ref* ref,
                                 double* record, int64_t record_ld, hbl_stream stream) {
@@ -592,6 +662,8 @@ hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out
     if (hbl_status st = check_bunch(z, n, ld, "moments")) return st;
     HBL_REQUIRE(n >= 1, "moments: need n >= 1");
     HBL_REQUIRE(out27 && ((uintptr_t)out27 & 7u) == 0, "moments: bad output pointer");
+    if (hbl_status st = check_device(z, bunch_bytes(n, ld), "moments")) return st;
+    if (hbl_status st = check_device(out27, 27 * sizeof(double), "moments output")) return st;
     double* ws = workspace(reduce_ws_bytes(n));
     if (!ws) { set_error(HBL_ENOMEM, "moments: workspace allocation failed"); return HBL_ENOMEM; }
     HBL_HIP(launch_moments(z, n, ld, ws, out27, (hipStream_t)stream));
@@ -604,6 +676,7 @@ hbl_status hbl_moments(const double* z, int64_t n, int64_t ld, double mean6[6], 
     if (hbl_status st = check_bunch(z, n, ld, "moments")) return st;
     HBL_REQUIRE(n >= 1, "moments: need n >= 1");
     HBL_REQUIRE(mean6 && cov21, "moments: NULL output");
+    if (hbl_status st = check_device(z, bunch_bytes(n, ld), "moments")) return st;
     const size_t wsb = reduce_ws_bytes(n) + 64 * sizeof(double);
     double* ws = workspace(wsb);
     if (!ws) { set_error(HBL_ENOMEM, "moments: workspace allocation failed"); return HBL_ENOMEM; }
@@ -959,6 +1032,8 @@ hbl_status surrogate_apply_impl(double* z, int64_t n, int64_t ld, const hbl_latt
         if (hbl_status st = check_gap(post, ref->gamma + m->dE_MeV / ref->mass_MeV, "surrogate_apply: exit"))
             return st;
     }
+    if (n > 0)
+        if (hbl_status st = check_device(z, bunch_bytes(n, ld), "surrogate_apply")) return st;
     if (n > 0) HBL_HIP(launch_mlp_infer(z, n, ld, m->d_img, m->norm, view_of(pre), view_of(post), (hipStream_t)stream));
     if (m->has_stage) {
         ref->gamma += m->dE_MeV / ref->mass_MeV;
@@ -991,8 +1066,14 @@ hbl_status hbl_surrogate_loss_grad(hbl_surrogate* m, const double* zin, const do
     if (hbl_status st = check_bunch(zin, 1, ld, "surrogate_loss_grad(in)")) return st;
     if (hbl_status st = check_bunch(zout, 1, ld, "surrogate_loss_grad(out)")) return st;
     HBL_REQUIRE(zin && zout, "surrogate_loss_grad: NULL pairs");
-    for (int32_t q = 0; q < batch; ++q) HBL_REQUIRE(idx[q] >= 0 && idx[q] < ld, "surrogate_loss_grad: index %d out of range", idx[q]);
+    int32_t imax = 0;
+    for (int32_t q = 0; q < batch; ++q) {
+        HBL_REQUIRE(idx[q] >= 0 && idx[q] < ld, "surrogate_loss_grad: index %d out of range", idx[q]);
+        imax = idx[q] > imax ? idx[q] : imax;
+    }
     if (!m->has_norm) { set_error(HBL_ESTATE, "surrogate_loss_grad: no normalisation set"); return HBL_ESTATE; }
+    if (hbl_status st = check_device(zin, bunch_bytes(imax + 1, ld), "surrogate_loss_grad(in)")) return st;
+    if (hbl_status st = check_device(zout, bunch_bytes(imax + 1, ld), "surrogate_loss_grad(out)")) return st;
     const int32_t nb = batch / 64;
     if (hbl_status st = ensure_train_scratch(m, nb, 2)) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -1043,6 +1124,8 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
     const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
     const int64_t n_test = n_pairs - n_train;
     HBL_REQUIRE(n_train >= cfg->batch, "surrogate_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);
+    if (hbl_status st = check_device(zin, bunch_bytes(n_pairs, ld), "surrogate_train(in)")) return st;
+    if (hbl_status st = check_device(zout, bunch_bytes(n_pairs, ld), "surrogate_train(out)")) return st;
     hipStream_t s = (hipStream_t)stream;
     // normalisation from the training split (§3), FP64 compensated moments
     double mi[6], ci[21], mo[6], co[21];
@@ -1476,6 +1559,7 @@ hbl_status prelu_apply_impl(double* z, int64_t n, int64_t ld, const hbl_lattice*
         if (hbl_status st = check_gap(post, ref->gamma + m->dE_MeV / ref->mass_MeV, "prelu_apply: exit")) return st;
     }
     if (n > 0) {
+        if (hbl_status st = check_device(z, bunch_bytes(n, ld), "prelu_apply")) return st;
         DenseNorm nm;
         for (int j = 0; j < 6; ++j) {
             nm.mu_in[j] = m->norm[j];
@@ -1641,9 +1725,14 @@ hbl_status hbl_prelu_loss_grad(hbl_prelu_net* m, const double* zin, const double
     if (hbl_status st = check_bunch(zin, 1, ld, "prelu_loss_grad(in)")) return st;
     if (hbl_status st = check_bunch(zout, 1, ld, "prelu_loss_grad(out)")) return st;
     HBL_REQUIRE(zin && zout, "prelu_loss_grad: NULL pairs");
-    for (int32_t q = 0; q < batch; ++q)
+    int32_t imax = 0;
+    for (int32_t q = 0; q < batch; ++q) {
         HBL_REQUIRE(idx[q] >= 0 && idx[q] < ld, "prelu_loss_grad: index %d out of range", idx[q]);
+        imax = idx[q] > imax ? idx[q] : imax;
+    }
     if (!m->has_norm) { set_error(HBL_ESTATE, "prelu_loss_grad: no normalisation set"); return HBL_ESTATE; }
+    if (hbl_status st = check_device(zin, bunch_bytes(imax + 1, ld), "prelu_loss_grad(in)")) return st;
+    if (hbl_status st = check_device(zout, bunch_bytes(imax + 1, ld), "prelu_loss_grad(out)")) return st;
     hipStream_t s = (hipStream_t)stream;
     if (hbl_status st = prelu_train_buffers(m, batch, 1, s)) return st;
     if (hbl_status st = prelu_repack_all(m, s)) return st;
@@ -1677,6 +1766,8 @@ hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zo
     const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
     const int64_t n_test = n_pairs - n_train;
     HBL_REQUIRE(n_train >= cfg->batch, "prelu_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);
+    if (hbl_status st = check_device(zin, bunch_bytes(n_pairs, ld), "prelu_train(in)")) return st;
+    if (hbl_status st = check_device(zout, bunch_bytes(n_pairs, ld), "prelu_train(out)")) return st;
     hipStream_t s = (hipStream_t)stream;
     double mi[6], ci[21], mo[6], co[21];
     if (hbl_status st = hbl_moments(zin, n_train, ld, mi, ci, stream)) return st;

@@ -76,6 +76,7 @@ def _load():
         "hbl_lattice_info": ([vp, dp, C.POINTER(i32)], st),
         "hbl_push_lattice": ([vp, i64, i64, vp, C.POINTER(Ref), C.c_uint32, vp], st),
         "hbl_apply_stage": ([vp, i64, i64, C.POINTER(Element), C.POINTER(Ref), vp, i64, vp], st),
+        "hbl_stage_newton_steps": ([C.POINTER(Element), C.POINTER(Ref), C.POINTER(i32)], st),
         "hbl_apply_stage_gaps": ([vp, i64, i64, vp, C.POINTER(Element), vp, C.POINTER(Ref), vp, i64, vp], st),
         "hbl_moments": ([vp, i64, i64, dp, dp, vp], st),
         "hbl_moments_async": ([vp, i64, i64, vp, vp], st),
@@ -155,12 +156,40 @@ def new_bunch(n: int, device="cuda"):
     return torch.empty((6, max(ld, 2)), dtype=torch.float64, device=device)
 
 
-def _bunch_args(z, n=None):
-    if z.dtype.itemsize != 8 or z.dim() != 2 or z.shape[0] != 6 or z.stride(1) != 1:
-        raise TypeError("bunch must be a (6, ld) float64 tensor with unit column stride")
+def _on_current_device(t, what):
+    """Raise unless tensor t lives on the current HIP device (the library
+    launches there; a host tensor or another device's memory would fault)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor, got one on {t.device}")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{what} is on {t.device}, the current device is cuda:{torch.cuda.current_device()}")
+
+
+def _bunch_args(z, n=None, what="bunch"):
+    torch = _torch()
+    if not isinstance(z, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if z.dtype != torch.float64 or z.dim() != 2 or z.shape[0] != 6 or z.stride(1) != 1:
+        raise TypeError(f"{what} must be a (6, ld) float64 tensor with unit column stride")
     ld = z.stride(0)
-    n = z.shape[1] if n is None else n
+    n = z.shape[1] if n is None else int(n)
+    if not 0 <= n <= z.shape[1]:
+        raise ValueError(f"{what}: n = {n} outside [0, {z.shape[1]}] (the tensor's particle count)")
+    _on_current_device(z, what)
     return C.c_void_p(z.data_ptr()), n, ld
+
+
+def _index_args(idx, limit, what):
+    import numpy as np
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    if idx.ndim != 1:
+        raise ValueError(f"{what}: indices must be one-dimensional")
+    if len(idx) and (idx.min() < 0 or idx.max() >= limit):
+        raise ValueError(f"{what}: indices must lie in [0, {limit})")
+    return idx
 
 
 def element(e) -> Element:
@@ -216,12 +245,20 @@ def apply_stage(z, stage, ref: Ref, record=None, n=None, stream=None, pre=None, 
     el = stage if isinstance(stage, Element) else element(stage)
     rp, rld = (None, 0)
     if record is not None:
-        rp, _, rld = _bunch_args(record, n)
+        rp, _, rld = _bunch_args(record, n, "record")
     if pre is None and post is None:
         _call("hbl_apply_stage", ptr, n, ld, C.byref(el), C.byref(ref), rp, rld, stream or current_stream())
     else:
         _call("hbl_apply_stage_gaps", ptr, n, ld, pre._h if pre else None, C.byref(el),
               post._h if post else None, C.byref(ref), rp, rld, stream or current_stream())
+
+
+def stage_newton_steps(stage, ref: Ref) -> int:
+    """Newton steps per substep the stage integrator will use (0 = divide)."""
+    el = stage if isinstance(stage, Element) else element(stage)
+    k = C.c_int32()
+    _call("hbl_stage_newton_steps", C.byref(el), C.byref(ref), C.byref(k))
+    return k.value
 
 
 def moments(z, n=None, stream=None):
@@ -232,9 +269,17 @@ def moments(z, n=None, stream=None):
     return list(m), list(c)
 
 
+def _out27_arg(out27):
+    torch = _torch()
+    _on_current_device(out27, "moments output")
+    if out27.dtype != torch.float64 or not out27.is_contiguous() or out27.numel() < 27:
+        raise TypeError("moments output must be a contiguous float64 device tensor of >= 27 elements")
+    return C.c_void_p(out27.data_ptr())
+
+
 def moments_async(z, out27, n=None, stream=None):
     ptr, n, ld = _bunch_args(z, n)
-    _call("hbl_moments_async", ptr, n, ld, C.c_void_p(out27.data_ptr()), stream or current_stream())
+    _call("hbl_moments_async", ptr, n, ld, _out27_arg(out27), stream or current_stream())
 
 
 def emittances(cov21):
@@ -302,8 +347,8 @@ class Surrogate:
     def train(self, zin, zout, n_pairs, batch=4096, epochs=1, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
               train_frac=0.7, shuffle_seed=0, max_steps=-1, lr_final=None, stream=None):
         import numpy as np
-        pin, _, ld = _bunch_args(zin, n_pairs)
-        pout, _, ldo = _bunch_args(zout, n_pairs)
+        pin, _, ld = _bunch_args(zin, n_pairs, "input pairs")
+        pout, _, ldo = _bunch_args(zout, n_pairs, "output pairs")
         if ldo != ld:
             raise ValueError("train: input and output pairs need the same leading dimension")
         cfg = TrainCfg(batch, epochs, max_steps, lr, lr if lr_final is None else lr_final, beta1, beta2, eps,
@@ -315,9 +360,11 @@ class Surrogate:
 
     def loss_grad(self, zin, zout, idx, stream=None):
         import numpy as np
-        pin, _, ld = _bunch_args(zin)
-        pout, _, _ = _bunch_args(zout)
-        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        pin, _, ld = _bunch_args(zin, what="input pairs")
+        pout, _, ldo = _bunch_args(zout, what="output pairs")
+        if ldo != ld:
+            raise ValueError("loss_grad: input and output pairs need the same leading dimension")
+        idx = _index_args(idx, min(zin.shape[1], zout.shape[1]), "loss_grad")
         g = np.empty(self.n_params, dtype=np.float32)
         loss = C.c_double()
         _call("hbl_surrogate_loss_grad", self._h, pin, pout, ld, idx.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -407,9 +454,11 @@ class PreluNet:
 
     def loss_grad(self, zin, zout, idx, stream=None):
         import numpy as np
-        pin, _, ld = _bunch_args(zin)
-        pout, _, _ = _bunch_args(zout)
-        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        pin, _, ld = _bunch_args(zin, what="input pairs")
+        pout, _, ldo = _bunch_args(zout, what="output pairs")
+        if ldo != ld:
+            raise ValueError("loss_grad: input and output pairs need the same leading dimension")
+        idx = _index_args(idx, min(zin.shape[1], zout.shape[1]), "loss_grad")
         g = np.empty(self.n_params, dtype=np.float32)
         loss = C.c_double()
         _call("hbl_prelu_loss_grad", self._h, pin, pout, ld, idx.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -419,8 +468,8 @@ class PreluNet:
     def train(self, zin, zout, n_pairs, batch=1200, epochs=1, lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-8,
               train_frac=0.7, shuffle_seed=0, max_steps=-1, lr_final=None, stream=None):
         import numpy as np
-        pin, _, ld = _bunch_args(zin, n_pairs)
-        pout, _, ldo = _bunch_args(zout, n_pairs)
+        pin, _, ld = _bunch_args(zin, n_pairs, "input pairs")
+        pout, _, ldo = _bunch_args(zout, n_pairs, "output pairs")
         if ldo != ld:
             raise ValueError("train: input and output pairs need the same leading dimension")
         cfg = TrainCfg(batch, epochs, max_steps, lr, lr if lr_final is None else lr_final, beta1, beta2, eps,
