@@ -484,7 +484,10 @@ int orc_mlp_init(const orc_shape* sh, uint64_t seed, float* params)
 
 /* Forward pass of one sample.  xin: raw input (6 doubles).  Stores the
  * network input actually used (act[0]), each hidden activation act[l] and the
- * normalised output yhat.  Mode 1 applies the GPU rounding points:
+ * normalised output yhat.  Mode 0 is the network of Eq. (3) in FP64 and is
+ * the parity reference.  Mode 1 FOLLOWS THE LIBRARY KERNEL (a secondary,
+ * kernel-specific check, not a statement of the method): it applies the
+ * kernel's own rounding points:
  *   hidden layers form the pre-activation scaled by c = 2/ln 2 (FP32 c),
  *   from FP32 c*w and c*b, and take tanh(ln2/2 * that);
  *   input: FP32 value split into bf16 hi + lo, first-layer (scaled) weights
@@ -661,6 +664,16 @@ int orc_epoch_perm(int64_t n, uint64_t seed, int64_t epoch, int64_t* perm)
     return 0;
 }
 
+/* Learning rate of optimizer step t (1-based) of `planned`: a half cosine
+ * from lr at the first step to lr_final at the last (constant when they are
+ * equal).  The paper and the benchmark definition name a rate but no
+ * schedule; the anneal is this build's reading. */
+double orc_lr_at(int64_t t, int64_t planned, double lr, double lr_final)
+{
+    if (planned <= 1 || lr_final == lr) return lr;
+    return lr_final + 0.5 * (lr - lr_final) * (1.0 + cos(M_PI * (double)(t - 1) / (double)(planned - 1)));
+}
+
 int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
                   const double* zin, const double* zout, int64_t n_pairs, int64_t ld,
                   int64_t batch, int64_t epochs, int64_t max_steps, double lr, double lr_final,
@@ -692,10 +705,7 @@ int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
             double loss;
             orc_mlp_loss_grad(sh, params, norm, mode, zin, zout, ld, perm + s * batch, batch, g, &loss);
             t++;
-            double lr_t = lr;
-            if (planned > 1 && lr_final != lr)
-                lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + cos(M_PI * (double)(t - 1) / (double)(planned - 1)));
-            orc_adam_step(np, params, m, v, g, t, lr_t, b1, b2, eps);
+            orc_adam_step(np, params, m, v, g, t, orc_lr_at(t, planned, lr, lr_final), b1, b2, eps);
             lsum += loss;
             done++;
         }

@@ -69,8 +69,11 @@ float orc_bf16(float x);
 typedef struct { int32_t n_in, width, hidden, n_out; } orc_shape;
 int64_t orc_mlp_nparams(const orc_shape* sh);
 int orc_mlp_init(const orc_shape* sh, uint64_t seed, float* params);
-/* norm: mu_in[6], sd_in[6], mu_out[6], sd_out[6] (FP64). mode 0 = FP64,
- * mode 1 = bfloat16 emulation of the GPU rounding points. */
+/* norm: mu_in[6], sd_in[6], mu_out[6], sd_out[6] (FP64). mode 0 = FP64, the
+ * network as defined (the parity reference, with the rounding-error models of
+ * mlp_error.py); mode 1 = an emulation that FOLLOWS THE LIBRARY KERNEL's own
+ * rounding points (its tanh scale fold and first-layer split included), kept
+ * as a secondary, kernel-specific check only. */
 int orc_mlp_apply(const orc_shape* sh, const float* params, const double* norm, int mode,
                   const double* zin, double* zout, int64_t n, int64_t ld);
 /* Loss (Eq. 4, normalised coordinates) and gradient over the pairs idx[0..b). */
@@ -95,6 +98,8 @@ int orc_prelu_apply(const orc_shape* sh, const float* params, const double* norm
 int orc_prelu_loss_grad(const orc_shape* sh, const float* params, const double* norm,
                         const double* zin, const double* zout, int64_t ld,
                         const int64_t* idx, int64_t b, double* grad, double* loss);
+/* Learning rate of step t (1-based) of `planned`: half cosine lr -> lr_final. */
+double orc_lr_at(int64_t t, int64_t planned, double lr, double lr_final);
 /* Full training loop; loss_log[2*e] = mean train loss, [2*e+1] = test loss. */
 int orc_mlp_train(const orc_shape* sh, float* params, double* norm, int mode,
                   const double* zin, const double* zout, int64_t n_pairs, int64_t ld,

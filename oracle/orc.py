@@ -79,6 +79,8 @@ def lib():
         L.orc_adam_step.argtypes = [i64, fp, dp, dp, dp, i64, C.c_double, C.c_double,
                                     C.c_double, C.c_double]
         L.orc_norm_stats.argtypes = [dp, dp, i64, i64, dp]
+        L.orc_lr_at.argtypes = [i64, i64, C.c_double, C.c_double]
+        L.orc_lr_at.restype = C.c_double
         L.orc_epoch_perm.argtypes = [i64, C.c_uint64, i64, C.POINTER(C.c_int64)]
         L.orc_mlp_train.argtypes = [C.POINTER(_Shape), fp, dp, C.c_int, dp, dp, i64, i64, i64, i64,
                                     i64, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
@@ -258,6 +260,10 @@ def norm_stats(zin, zout, n_train):
     norm = np.empty(24)
     _check(lib().orc_norm_stats(_dp(zin), _dp(zout), n_train, zin.shape[1], _dp(norm)), "norm_stats")
     return norm
+
+
+def lr_at(t, planned, lr, lr_final):
+    return float(lib().orc_lr_at(t, planned, lr, lr_final))
 
 
 def epoch_perm(n, seed, epoch):
