@@ -205,7 +205,13 @@ hbl_status hbl_compare(const double* zs, const double* zf, int64_t n, int64_t ld
  * Eq. (4) with Adam.  The kernels support the shape {6, 64, 3, 6} (three
  * hidden layers of 64).  Dense layers run on the matrix cores in bf16 with
  * FP32 accumulation; tanh and normalisation in FP32/FP64; the output layer
- * result stays FP32 and is de-normalised in FP64.  FP32 master parameters,
+ * result stays FP32 and is de-normalised in FP64.  Rounding points, which
+ * bound how far results may lie from the FP64 network: hidden and output
+ * layers take bf16 weights and bf16 activations (8 significant bits); the
+ * first layer keeps 16 significant bits of its FP32 input and weights (a
+ * bf16 hi + lo split); tanh has absolute error below 2^-20; in training, the
+ * errors back-propagated into layers 1..3 and the weights they meet enter the
+ * products in bf16, the first layer's weight gradient is FP32.  FP32 master parameters,
  * flat layout A_0 (64x6, row-major [out][in]), b_0, A_1, b_1, A_2, b_2, A_3
  * (6x64), b_3: 9158 floats. */
 typedef struct hbl_surrogate hbl_surrogate;

@@ -1,13 +1,16 @@
 """GPU parity of the staged beamline (§4, Fig. 1: stages joined by transport
 gaps): the fine-step chain against the oracle chain on sampled particles,
 and the surrogate chain against the oracle evaluating the same networks (set
-from oracle-made parameters) in its bf16-emulation mode.  The sampled
-particles start from the oracle's fill of the same seed and indices."""
+from oracle-made parameters) in FP64, within the spread the networks'
+documented rounding points allow.  The sampled particles start from the
+oracle's fill of the same seed and indices."""
 import numpy as np
 import pytest
 
 import workloads as W
 from gpu_util import rel_err
+from oracle import mlp_error as me
+from rounding_contract import SURROGATE
 
 pytestmark = pytest.mark.gpu
 
@@ -107,7 +110,11 @@ def oracle_surrogates(hbl, orc, wl, chain, seed0):
     return out
 
 
-def oracle_surrogate_chain(orc, wl, nets, c):
+def oracle_surrogate_chain(orc, wl, nets, c, mode=0, rng=None):
+    """The chain in the oracle: its lattice maps between the stages and each
+    stage's network in FP64 (mode 0), in the kernel-emulating mode (mode 1),
+    or (rng given) in FP64 with the documented rounding points perturbed at
+    random (one Monte-Carlo-arithmetic pass)."""
     oref = orc.Ref.from_energy(wl.E_MeV)
     k = 0
     for seg in wl.beamline:
@@ -115,7 +122,11 @@ def oracle_surrogate_chain(orc, wl, nets, c):
             orc.push(c, seg, oref)
         else:
             p, norm = nets[k]
-            c = orc.mlp_apply(orc.shape(), p, norm, c, mode=1)
+            if rng is None:
+                c = orc.mlp_apply(orc.shape(), p, norm, c, mode=mode)
+            else:
+                y = me.perturbed_forward(me.unpack(p, 64, 3), me.normalise_in(c, norm), SURROGATE, rng)[2]
+                c = np.ascontiguousarray(norm[12:18, None] + norm[18:24, None] * y.T)
             oref.gamma += seg.dE_MeV / oref.mass_MeV
             oref.s += seg.L
             k += 1
@@ -124,8 +135,12 @@ def oracle_surrogate_chain(orc, wl, nets, c):
 
 @pytest.mark.parametrize("n,n_stages", [(50_001, 2), (25_000_000, 4)])
 def test_surrogate_chain_parity(hbl, orc, n, n_stages):
-    """The chain composes lattice gaps and surrogate inference exactly as the
-    oracle composes its own, small and at the benchmark's full size."""
+    """The chain composes lattice gaps and surrogate inference as the oracle
+    composes its own, small and at the benchmark's full size.  Reference: the
+    oracle chain with FP64 networks.  Allowance, per coordinate and sampled
+    particle: 8 standard deviations of 24 Monte-Carlo-arithmetic passes of
+    the oracle chain with the networks' documented rounding points randomised
+    (the lattices between the stages are FP64 on both sides)."""
     from paper_2402_17248_amd.chain import Chain
     wl = W.c5_chain(n=n, nsub=300, n_stages=n_stages)
     chain = Chain(wl.beamline, wl.E_MeV)
@@ -134,16 +149,23 @@ def test_surrogate_chain_parity(hbl, orc, n, n_stages):
     z, c = seed_bunch(hbl, wl, n, idx, orc)
     ref = chain.run(z, n=n, use_surrogates=True)
     g = sample(z, idx)
-    c, oref = oracle_surrogate_chain(orc, wl, nets, c)
+    c64, oref = oracle_surrogate_chain(orc, wl, nets, c.copy())
     assert abs(ref.gamma / oref.gamma - 1) < 1e-15 and abs(ref.s - oref.s) < 1e-12
-    # bf16 networks in sequence: rounding-boundary flips (see test_gpu_surrogate)
-    # move ~2 % of the particles per network; the lattices between them are exact
-    sd = np.sqrt(np.mean(c * c, axis=1))[:, None]
-    d = np.abs(g - c) / sd
-    moved = np.mean(d.max(axis=0) > 1e-3)
-    assert np.median(d) < 1e-5, np.median(d)
-    assert moved < 0.05 * n_stages, moved
-    assert d.max() < 0.1 * n_stages, d.max()
+    runs = np.array([oracle_surrogate_chain(orc, wl, nets, c.copy(), rng=np.random.default_rng(900 + k))[0]
+                     for k in range(24)])
+    sig = runs.std(axis=0, ddof=1)
+    sd = np.sqrt(np.mean(c64 * c64, axis=1))[:, None]
+    d = np.abs(g - c64)
+    r = d / (sig + 1e-12 * sd)
+    print(f"surrogate chain ({n_stages} stages): |gpu - fp64| max {np.max(d / sd):.2e} rms, "
+          f"|d|/sigma max {r.max():.2f} median {np.median(r):.2f}", flush=True)
+    assert np.all(r <= 8.0), r.max()
+    # secondary: the kernel-emulating mode, same rounding points with FP64 sums
+    c1, _ = oracle_surrogate_chain(orc, wl, nets, c.copy(), mode=1)
+    d1 = np.abs(g - c1) / sd
+    print(f"vs kernel emulation: median {np.median(d1):.2e} max {d1.max():.2e}", flush=True)
+    assert np.median(d1) < 1e-5, np.median(d1)
+    assert d1.max() < 0.05 * n_stages, d1.max()
 
 
 def test_pairs_record_stage_input(hbl, orc):

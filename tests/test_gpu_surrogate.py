@@ -1,13 +1,24 @@
-"""GPU parity of the surrogate network (§3 Eq. 3-4, Adam) against the CPU
-oracle's bf16-emulation mode, through the C ABI.
+"""GPU parity of the surrogate network (§3 Eq. 3-4, Adam) through the C ABI,
+against the FP64 network of the CPU oracle.
 
-Expected differences (the oracle accumulates in FP64 and evaluates tanh
-exactly; the GPU accumulates in FP32 on the matrix cores and evaluates tanh
-from exp2/reciprocal approximations, ~1e-7 relative): a value that lands
-within ~1e-7 of a bf16 rounding boundary rounds the other way, a one-ulp
-(2^-8 relative) change of one activation in ~1e-4 of all activations.  Most
-outputs therefore agree to ~1e-6 (normalised units) and a few percent of the
-particles move by up to ~1e-2."""
+Reference: the oracle's FP64 evaluation (mode 0), the network as defined.
+Allowance: what the library's documented rounding points allow
+(tests/rounding_contract.py; oracle/mlp_error.py derives it):
+
+* forward, per output and particle: within the first-order worst-case bound B
+  and within LAM = 7 probabilistic scales S (independent rounding errors,
+  Hoeffding: each output exceeds 7 S with probability <= 5e-11), and the
+  median distance below one S;
+* gradient, per parameter: within 8 standard deviations of a 64-member
+  Monte-Carlo-arithmetic ensemble of the FP64 gradient with those rounding
+  points randomised (plus the FP32 rounding of the returned value), and per
+  tensor a relative Frobenius distance below 3 x the ensemble's.
+
+A secondary check per test compares with the oracle's kernel-emulating mode
+(mode 1), which follows the kernel's own rounding (its tanh scale fold and
+first-layer split) with FP64 sums and an exact tanh: there the two agree to
+~1e-6 except where a value within ~1e-7 of a bf16 rounding boundary rounds
+the other way on one side."""
 import os
 import tempfile
 
@@ -16,6 +27,8 @@ import pytest
 
 import workloads as W
 from gpu_util import to_dev, to_host
+from oracle import mlp_error as me
+from rounding_contract import LAM, SURROGATE
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +62,23 @@ def perturbed(orc, seed):
     return (p + 0.05 * rng.standard_normal(p.shape)).astype(np.float32)
 
 
+def check_forward(g, xin, p, norm, what):
+    """g: GPU output bunch (6, m) for raw inputs xin (6, m).  Returns the
+    normalised distance from the FP64 network and the scales, after checking
+    the bound and the probabilistic scale."""
+    net = me.unpack(p, 64, 3)
+    y, B, S = me.forward_bound(net, me.normalise_in(xin, norm), SURROGATE)
+    d = np.abs(me.normalise_out(g, norm) - y)
+    r = d / S
+    print(f"{what}: |gpu - fp64| max {d.max():.3e} median {np.median(d):.3e}; bound B median "
+          f"{np.median(B):.3e}, max d/B {np.max(d / B):.3f}; d/S max {r.max():.2f} median {np.median(r):.3f}",
+          flush=True)
+    assert np.all(d <= B), np.max(d / B)
+    assert np.all(r <= LAM), r.max()
+    assert np.median(r) < 1.0, np.median(r)
+    return d
+
+
 def test_init_matches_oracle(hbl, orc):
     for seed in (0, 101, 2**40 + 3):
         s = hbl.Surrogate(seed)
@@ -66,12 +96,17 @@ def test_forward_parity(hbl, orc, pairs):
     z = rec[:, :m + 1].clone()
     s.apply(z, n=m)
     g = to_host(z, m)
-    c = orc.mlp_apply(orc.shape(), p, norm, np.ascontiguousarray(xin[:, :m]), mode=1)
-    d = np.abs(g - c) / norm[18:24, None]
-    frac_off = np.mean(d.max(axis=0) > 1e-4)
-    assert d.max() < 5e-2, d.max()
-    assert frac_off < 0.05, frac_off
-    assert np.median(d) < 1e-6
+    x = np.ascontiguousarray(xin[:, :m])
+    check_forward(g, x, p, norm, "forward 10001")
+    # secondary: the kernel-emulating mode (same rounding points, FP64 sums, exact tanh)
+    c = orc.mlp_apply(orc.shape(), p, norm, x, mode=1)
+    d1 = np.abs(g - c) / norm[18:24, None]
+    frac = np.mean(d1.max(axis=0) > 1e-4)
+    print(f"vs kernel emulation: median {np.median(d1):.2e} max {d1.max():.2e}, particles beyond 1e-4 {frac:.4f}",
+          flush=True)
+    assert np.median(d1) < 1e-6
+    assert d1.max() < 1e-2
+    assert frac < 0.01
 
 
 @pytest.mark.parametrize("m", [1, 63, 64, 65, 130])
@@ -85,9 +120,10 @@ def test_forward_ragged_sizes(hbl, orc, pairs, m):
     z = rec.clone()
     s.apply(z, n=m)
     g = to_host(z, n)
-    c = orc.mlp_apply(orc.shape(), p, norm, np.ascontiguousarray(xin[:, :m]), mode=1)
-    d = np.abs(g[:, :m] - c) / norm[18:24, None]
-    assert d.max() < 5e-2
+    net = me.unpack(p, 64, 3)
+    y, B, S = me.forward_bound(net, me.normalise_in(np.ascontiguousarray(xin[:, :m]), norm), SURROGATE)
+    d = np.abs(me.normalise_out(np.ascontiguousarray(g[:, :m]), norm) - y)
+    assert np.all(d <= B) and np.all(d <= LAM * S)
     assert np.array_equal(g[:, m:], xin[:, m:])          # particles past n untouched
 
 
@@ -109,17 +145,40 @@ def test_forward_full_size_sampled(hbl, orc, pairs):
     x0 = orc.fill_gaussian(0, W.C4_INFER_SEED, mean, sd, idx=idx)   # same particles, the oracle's fill
     s.apply(z, n=N)
     g = np.ascontiguousarray(z[:, ti].cpu().numpy())
-    c = orc.mlp_apply(orc.shape(), p, norm, x0, mode=1)
-    d = np.abs(g - c) / norm[18:24, None]
-    assert d.max() < 5e-2 and np.mean(d.max(axis=0) > 1e-4) < 0.05
+    check_forward(g, x0, p, norm, "forward 1e7 sampled")
+
+
+TENSORS = [("W0", 0, 384), ("b0", 384, 448), ("W1", 448, 4544), ("b1", 4544, 4608), ("W2", 4608, 8704),
+           ("b2", 8704, 8768), ("W3", 8768, 9152), ("b3", 9152, 9158)]
 
 
 def rel_fro(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
-TENSORS = [("W0", 0, 384), ("b0", 384, 448), ("W1", 448, 4544), ("b1", 4544, 4608), ("W2", 4608, 8704),
-           ("b2", 8704, 8768), ("W3", 8768, 9152), ("b3", 9152, 9158)]
+def mca_gradient(p, norm, xin, xout, idx, K=64):
+    """FP64 loss and gradient of the batch idx, and the spread of K
+    Monte-Carlo-arithmetic passes with the documented rounding points."""
+    net = me.unpack(p, 64, 3)
+    x = me.normalise_in(np.ascontiguousarray(xin[:, idx]), norm)
+    yt = me.normalise_out(np.ascontiguousarray(xout[:, idx]), norm)
+    loss, g = me.loss_grad(net, x, yt)
+    draws = [me.loss_grad(net, x, yt, SURROGATE, np.random.default_rng(7000 + k)) for k in range(K)]
+    Ls = np.array([d[0] for d in draws])
+    G = np.array([d[1] for d in draws])
+    return loss, g, Ls.std(ddof=1), G.std(axis=0, ddof=1)
+
+
+def check_gradient(gg, g64, sig, what):
+    d = np.abs(gg.astype(np.float64) - g64)
+    allow = 8.0 * sig + 2.0 * 2.0 ** -24 * np.abs(g64) + 1e-12 * np.abs(g64).max()
+    print(f"{what}: max |dg|/sigma {np.max(d / np.maximum(sig, 1e-300)):.2f}, median "
+          f"{np.median(d / np.maximum(sig, 1e-300)):.2f}", flush=True)
+    assert np.all(d <= allow), np.argmax(d / allow)
+    for name, a, b in TENSORS:
+        rf = rel_fro(gg[a:b].astype(np.float64), g64[a:b])
+        spread = np.linalg.norm(sig[a:b]) / np.linalg.norm(g64[a:b])
+        assert rf < 3.0 * spread + 1e-6, (name, rf, spread)
 
 
 def test_gradient_parity(hbl, orc, pairs):
@@ -131,18 +190,24 @@ def test_gradient_parity(hbl, orc, pairs):
     s.set_norm(norm)
     idx = np.random.default_rng(4).choice(n, 512, replace=False).astype(np.int32)
     loss_g, g = s.loss_grad(rec, out, idx)
-    loss_o, go = orc.mlp_loss_grad(orc.shape(), p, norm, xin, xout, idx.astype(np.int64), mode=1)
-    assert abs(loss_g / loss_o - 1) < 1e-5
-    for name, a, b in TENSORS:
-        assert rel_fro(g[a:b].astype(np.float64), go[a:b]) < 1e-2, name
-    # and against the exact FP64 gradient (the bf16 rounding points move it by ~1e-2)
-    _, g64 = orc.mlp_loss_grad(orc.shape(), p, norm, xin, xout, idx.astype(np.int64), mode=0)
-    assert rel_fro(g.astype(np.float64), g64) < 5e-2
+    loss64, g64, sig_l, sig = mca_gradient(p, norm, xin, xout, idx)
+    print(f"loss gpu {loss_g:.8e} fp64 {loss64:.8e} (|d|/sigma {abs(loss_g - loss64) / sig_l:.2f})", flush=True)
+    assert abs(loss_g - loss64) <= 8.0 * sig_l + 1e-7 * loss64
+    check_gradient(g, g64, sig, "gradient 512")
+    # secondary: the kernel-emulating mode
+    _, go = orc.mlp_loss_grad(orc.shape(), p, norm, xin, xout, idx.astype(np.int64), mode=1)
+    worst = max(rel_fro(g[a:b].astype(np.float64), go[a:b]) for _, a, b in TENSORS)
+    print(f"vs kernel emulation: worst per-tensor relative Frobenius {worst:.2e}", flush=True)
+    assert worst < 1e-3
 
 
 def test_first_adam_step_and_epoch_order(hbl, orc, pairs):
     """One optimizer step of training equals the oracle's Adam applied to the
-    gradient of the first batch of the oracle's epoch-0 Fisher-Yates order."""
+    FP64 gradient of the first batch of the oracle's epoch-0 Fisher-Yates
+    order.  Adam's first step moves a parameter by lr g/(|g| + eps) ~ lr
+    sign(g): it must agree wherever the FP64 gradient is farther from zero
+    than the rounding can move it (8 ensemble deviations); elsewhere the
+    sign may differ and the step by at most 2 lr."""
     n, rec, out, xin, xout, _, _ = pairs
     s = hbl.Surrogate(11)
     p0 = orc.mlp_init(orc.shape(), 11)
@@ -150,28 +215,34 @@ def test_first_adam_step_and_epoch_order(hbl, orc, pairs):
     s.train(rec, out, n, batch=64, epochs=1, lr=1e-3, train_frac=0.7, shuffle_seed=77, max_steps=1)
     p1 = s.get_params().astype(np.float64)
     ntr = int(round(0.7 * n))
-    # the training normalisation is the oracle's over the training split
     on = orc.norm_stats(xin, xout, ntr)
     assert np.allclose(s.get_norm(), on, rtol=1e-13, atol=0)
     first = orc.epoch_perm(ntr, 77, 0)[:64]
-    _, g = orc.mlp_loss_grad(orc.shape(), p0, on, xin, xout, first.astype(np.int64), mode=1)
-    want, _, _ = orc.adam_step(p0, np.zeros(len(p0)), np.zeros(len(p0)), g, 1, lr=1e-3)
-    # Adam's first step moves a parameter by lr g / (|g| + eps), i.e. lr sign(g) unless
-    # |g| is ~eps: another batch would change most signs; the bf16 rounding points
-    # of the two sides may flip a few near-zero gradients
+    _, g64, _, sig = mca_gradient(p0, on, xin, xout, first)
+    want, _, _ = orc.adam_step(p0, np.zeros(len(p0)), np.zeros(len(p0)), g64, 1, lr=1e-3)
     d = np.abs(p1 - want)
-    assert np.mean(d > 1e-6) < 0.01, np.mean(d > 1e-6)
+    firm = np.abs(g64) > 8.0 * sig + 1e-6 * np.abs(g64).max()
+    print(f"first Adam step: {firm.mean():.3f} of the parameters have a firm gradient sign; "
+          f"max step difference there {d[firm].max():.2e}", flush=True)
+    assert firm.mean() > 0.5
+    assert np.all(d[firm] <= 1e-6)
     assert d.max() <= 2e-3 + 1e-6
 
 
 def test_training_curve_matches_oracle(hbl, orc, pairs):
+    """Three epochs of the same recipe (same epoch orders and rates) on the
+    GPU and in the oracle's FP64 training: the per-epoch training and test
+    losses agree to 10 % (the two runs take different rounding at every step,
+    and Adam's normalised steps let small gradient differences move the
+    parameters by up to lr each)."""
     n, rec, out, xin, xout, _, _ = pairs
     s = hbl.Surrogate(12)
     p0 = orc.mlp_init(orc.shape(), 12)
     assert np.array_equal(s.get_params(), p0.astype(np.float32))
     log = s.train(rec, out, n, batch=256, epochs=3, lr=3e-3, lr_final=3e-4, shuffle_seed=5)
     _, _, olog = orc.mlp_train(orc.shape(), p0, xin, xout, batch=256, epochs=3, lr=3e-3, lr_final=3e-4,
-                               shuffle_seed=5, mode=1)
+                               shuffle_seed=5, mode=0)
+    print("loss log gpu", log.tolist(), "oracle fp64", olog.tolist(), flush=True)
     assert np.all(np.isfinite(log))
     assert log[-1, 1] < 0.7 * log[0, 1]
     assert np.all(np.abs(log / olog - 1) < 0.1), (log, olog)
