@@ -13,7 +13,14 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liborc.so")
+# ORC_SANITIZE=1 builds and loads an AddressSanitizer + UndefinedBehaviorSanitizer
+# copy (liborc_san.so); the interpreter then needs the sanitizer runtimes
+# preloaded, e.g. LD_PRELOAD="$(gcc -print-file-name=libasan.so)
+# $(gcc -print-file-name=libubsan.so)" ASAN_OPTIONS=detect_leaks=0.
+_SANITIZE = os.environ.get("ORC_SANITIZE", "") not in ("", "0")
+_SO = os.path.join(_HERE, "liborc_san.so" if _SANITIZE else "liborc.so")
+_SAN_FLAGS = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=all"]
 MEC2_MEV = 0.51099895000   # electron rest energy (CODATA 2018)
 
 
@@ -21,6 +28,7 @@ def build(force: bool = True) -> str:
     """Compile orc.c into liborc.so with gcc (FP64, no contraction, no fast-math)."""
     if force or not os.path.exists(_SO):
         cmd = ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+               *(_SAN_FLAGS if _SANITIZE else []),
                "-o", _SO + ".tmp", os.path.join(_HERE, "orc.c"), "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_SO + ".tmp", _SO)
