@@ -187,6 +187,21 @@ hbl_status hbl_moments(const double* z, int64_t n, int64_t ld, double mean6[6], 
  * out27 (8-byte aligned). */
 hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out27,
                              hbl_stream stream);
+/* ASYNC, allocates nothing.  For callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and kernels as hbl_moments_async, with
+ * identical results, but the reduction's scratch is a fixed array of
+ * 442,800 bytes that the library holds in each device's memory until the
+ * process ends (looked up on a device's first call; no hipMalloc, hipFree or
+ * allocating library call is made).  Every n >= 1 fits in it (the reduction
+ * grid is capped); a size that did not would be rejected with HBL_EINVAL
+ * before anything is enqueued.  All calls on one device share that device's
+ * array and nothing in it needs clearing between calls: two calls that can
+ * overlap on one device (different streams, or different threads) race on
+ * it, so keep them on one stream.  The scratch is not shared with the other
+ * reductions' workspace. */
+hbl_status hbl_moments_async_noalloc(const double* z, int64_t n, int64_t ld, double* out27,
+                                     hbl_stream stream);
 /* Host only.  Geometric RMS emittances of (x,px), (y,py), (t,pt),
  * eps = sqrt(<dx^2><dpx^2> - <dx dpx>^2) (§4). */
 hbl_status hbl_emittances(const double cov21[21], double eps3[3]);

@@ -670,6 +670,22 @@ hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out
     return HBL_OK;
 }
 
+hbl_status hbl_moments_async_noalloc(const double* z, int64_t n, int64_t ld, double* out27, hbl_stream stream) {
+    clear_error();
+    if (hbl_status st = check_bunch(z, n, ld, "moments_async_noalloc")) return st;
+    HBL_REQUIRE(n >= 1, "moments_async_noalloc: need n >= 1");
+    HBL_REQUIRE(out27 && ((uintptr_t)out27 & 7u) == 0, "moments_async_noalloc: bad output pointer");
+    const size_t need = reduce_ws_bytes(n), have = reduce_scratch_bytes();
+    HBL_REQUIRE(need <= have, "moments_async_noalloc: n = %lld needs %zu bytes of scratch, more than the %zu reserved",
+                (long long)n, need, have);
+    if (hbl_status st = check_device(z, bunch_bytes(n, ld), "moments_async_noalloc")) return st;
+    if (hbl_status st = check_device(out27, 27 * sizeof(double), "moments_async_noalloc output")) return st;
+    double* ws = nullptr;
+    HBL_HIP(reduce_scratch(&ws));
+    HBL_HIP(launch_moments(z, n, ld, ws, out27, (hipStream_t)stream));
+    return HBL_OK;
+}
+
 hbl_status hbl_moments(const double* z, int64_t n, int64_t ld, double mean6[6], double cov21[21],
                        hbl_stream stream) {
     clear_error();

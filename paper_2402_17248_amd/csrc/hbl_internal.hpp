@@ -88,6 +88,10 @@ hipError_t launch_stage(double* z, int64_t n, int64_t ld, double* rec, int64_t r
 
 // Reductions.  `ws` is device scratch of at least reduce_ws_bytes(n) bytes.
 size_t reduce_ws_bytes(int64_t n);
+// The library's fixed per-device reduction scratch (no allocation): its size,
+// and its address on the current device (looked up once per device).
+size_t reduce_scratch_bytes();
+hipError_t reduce_scratch(double** out);
 hipError_t launch_moments(const double* z, int64_t n, int64_t ld, double* ws, double* out27,
                           hipStream_t s);
 hipError_t launch_diff2(const double* zs, const double* zf, int64_t n, int64_t ld, double* ws,

@@ -14,6 +14,8 @@
 // Compiled with -ffp-contract=off: the TwoSum sequences must not be fused.
 #include "hbl_internal.hpp"
 
+#include <mutex>
+
 namespace hbl {
 namespace {
 
@@ -275,7 +277,38 @@ int reduce_grid(int64_t n) {
     return (int)g;
 }
 
+// Fixed scratch of the no-allocation moments call: the workspace of the
+// largest grid (kMaxBlocks block partials, then the totals; 27 double-double
+// values each, 442,800 bytes), one copy in every device's memory for the life
+// of the process.  Host code never names this array as an address: each
+// device's copy is looked up once with hipGetSymbolAddress (scratch_pointer).
+constexpr size_t kScratchDD = (size_t)(kMaxBlocks + 1) * 27;
+static __device__ __align__(256) DD scratch[kScratchDD];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
 }  // namespace
+
+size_t reduce_scratch_bytes() { return kScratchDD * sizeof(DD); }
+
+hipError_t reduce_scratch(double** out) {
+    *out = nullptr;
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    if (d < 0 || d >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[d]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // this device's copy (device d is current)
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[d] = p;
+    }
+    *out = static_cast<double*>(g_scratch_ptr[d]);
+    return hipSuccess;
+}
 
 size_t reduce_ws_bytes(int64_t n) {
     return ((size_t)reduce_grid(n) + 1) * 27 * sizeof(DD);   // block partials, then the totals

@@ -80,6 +80,7 @@ def _load():
         "hbl_apply_stage_gaps": ([vp, i64, i64, vp, C.POINTER(Element), vp, C.POINTER(Ref), vp, i64, vp], st),
         "hbl_moments": ([vp, i64, i64, dp, dp, vp], st),
         "hbl_moments_async": ([vp, i64, i64, vp, vp], st),
+        "hbl_moments_async_noalloc": ([vp, i64, i64, vp, vp], st),
         "hbl_emittances": ([dp, dp], st),
         "hbl_compare": ([vp, vp, i64, i64, dp, dp, dp, vp], st),
         "hbl_surrogate_create": ([C.POINTER(MlpShape), C.c_uint64, C.POINTER(vp)], st),
@@ -280,6 +281,12 @@ def _out27_arg(out27):
 def moments_async(z, out27, n=None, stream=None):
     ptr, n, ld = _bunch_args(z, n)
     _call("hbl_moments_async", ptr, n, ld, _out27_arg(out27), stream or current_stream())
+
+
+def moments_async_noalloc(z, out27, n=None, stream=None):
+    """hbl_moments_async through the library's fixed scratch (no allocation)."""
+    ptr, n, ld = _bunch_args(z, n)
+    _call("hbl_moments_async_noalloc", ptr, n, ld, _out27_arg(out27), stream or current_stream())
 
 
 def emittances(cov21):

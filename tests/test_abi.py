@@ -118,6 +118,10 @@ def test_moments_and_compare_reject(hbl):
     assert hbl.lib.hbl_moments(BAD, 4, 4, None, c, None) == hbl.HBL_EINVAL
     r, e = _d6(), (C.c_double * 3)()
     assert hbl.lib.hbl_compare(BAD, None, 4, 4, r, m, e, None) == hbl.HBL_EINVAL
+    for args, frag in (((BAD, 0, 0, BAD), "n >= 1"), ((BAD, 4, 4, None), "output pointer"),
+                       ((BAD, 4, 4, C.c_void_p(0x1004)), "output pointer"), ((BAD, 4, 3, BAD), "ld")):
+        assert hbl.lib.hbl_moments_async_noalloc(*args, None) == hbl.HBL_EINVAL
+        assert frag in hbl.lib.hbl_last_error().decode()
 
 
 def test_emittances_host_only(hbl):
