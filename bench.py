@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--prelu-epochs", type=int, default=60,
                     help="epochs of the paper-shaped 3 x 700 surrogate trained with the paper's recipe")
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
+    ap.add_argument("--seed-sets", type=int, default=3,
+                    help="init/shuffle seed sets per stage for the per-stage accuracy spread (set 0 = the chain's)")
     ap.add_argument("--only-paper-shapes", action="store_true",
                     help="run only the paper-shaped PReLU surrogate studies (inference and training)")
     ap.add_argument("--only-configs", action="store_true",
@@ -147,59 +149,168 @@ def time_events(torch, fn, iters, setup=None):
     return total / iters * 1e-3
 
 
-def cpu_baseline(wl, chain, budget_s):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    the staged beamline with the trained surrogates evaluated by the oracle's
-    FP64 network.  Serial on one core, then the same per-particle code on a
-    thread pool over contiguous particle ranges (the oracle keeps no global
-    state; ctypes releases the interpreter lock during its calls)."""
+def host_cpu():
+    """What the CPU legs ran on: the model from /proc/cpuinfo, the logical
+    CPU count, the CPUs this process may run on, and the worker threads used
+    (the host's share per GPU is 16 threads, whatever the machine holds)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    threads = max(1, min(16, usable))
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": usable, "threads": threads,
+            "threads_note": "the GPU host grants 16 CPU threads per GPU; the pool is capped there"}
+
+
+def cpu_leg(make, run, budget_s, n_max, threads, per_particle=None, min_s=0.25):
+    """Time the oracle's run(z) on make(m, i0) bunches: serially on one core
+    (sample sized to ~budget_s / 2), then on `threads` worker threads over
+    contiguous particle ranges (threads x the serial sample, capped at
+    n_max).  A run shorter than min_s is repeated on fresh copies of its
+    bunch until it is not.  Bunch generation and copies are not timed.
+    Returns particles/s both ways and the samples."""
+    import math
     from concurrent.futures import ThreadPoolExecutor
 
+    def timed(zs):
+        t0 = time.perf_counter()
+        for z in zs:
+            run(z)
+        return time.perf_counter() - t0
+
+    t_small = timed([make(64, 0)]) / 64
+    m1 = int(max(64, min(n_max, 0.5 * budget_s / max(t_small, 1e-12))))
+    z1 = make(m1, 0)
+    t1 = timed([z1.copy()])
+    r1 = max(1, math.ceil(min_s / max(t1, 1e-9))) if t1 < min_s else 1
+    if r1 > 1:
+        t1 = timed([z1.copy() for _ in range(r1)])
+    m2 = min(n_max, m1 * threads)
+    per = (m2 + threads - 1) // threads
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        chunks = list(ex.map(lambda i: make(min(per, m2 - i), i), range(0, m2, per)))
+        r2 = 1
+        while True:
+            work = [[c.copy() for _ in range(r2)] for c in chunks]
+            t0 = time.perf_counter()
+            list(ex.map(timed, work))
+            t2 = time.perf_counter() - t0
+            if t2 >= min_s or r2 >= 1024:
+                break
+            r2 *= 2
+    out = {"serial_particles_per_s": r1 * m1 / t1, "serial_sample": m1, "serial_repeats": r1, "serial_s": t1,
+           "threads_particles_per_s": r2 * m2 / t2, "threads_sample": m2, "threads_repeats": r2,
+           "threads_s": t2, "threads": threads}
+    if per_particle:
+        for k, v in per_particle.items():
+            out[f"serial_{k}_per_s"] = v * out["serial_particles_per_s"]
+            out[f"threads_{k}_per_s"] = v * out["threads_particles_per_s"]
+    return out
+
+
+def cpu_baseline(wl, chain, budget_s):
+    """The oracle, as it stands, timed on the host's cores on bounded samples
+    of the same workloads (the oracle keeps no global state; ctypes releases
+    the interpreter lock during its calls, so particle ranges run in parallel
+    on a thread pool).  Headline leg: the staged beamline with the trained
+    surrogates evaluated by the oracle's FP64 network.  Further legs: the
+    fine-step staged chain (a seeded 1e6-particle subset on all threads,
+    extrapolated linearly to the full bunch and labelled so), the single
+    fine-step stage (C3) and one surrogate stage, the FODO cell (C1) and the
+    58-element lattice (C2)."""
     import numpy as np
 
     import oracle
+    import workloads as W
 
+    host = host_cpu()
+    T = host["threads"]
     params = [s.get_params() for s in chain.surrogates]
     norms = [np.array(s.get_norm()) for s in chain.surrogates]
     sh = oracle.shape()
     oracle.lib()
 
-    def fill(m, i0=0):
-        return oracle.fill_gaussian(m, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, i0=i0)
+    def filler(w):
+        return lambda m, i0=0: oracle.fill_gaussian(m, w.bunch.seed, (0.0,) * 6, w.bunch.sigma, i0=i0)
 
-    def track(z):
-        ref = oracle.Ref.from_energy(wl.E_MeV)
-        k = 0
-        for seg in wl.beamline:
-            if isinstance(seg, list):
-                oracle.push(z, seg, ref)
-            else:
-                z = oracle.mlp_apply(sh, params[k], norms[k], z, mode=0)
-                ref.gamma += seg.dE_MeV / ref.mass_MeV
-                k += 1
-        return z
+    def tracker(w, use_sur):
+        def track(z):
+            ref = oracle.Ref.from_energy(w.E_MeV)
+            k = 0
+            for seg in w.beamline:
+                if isinstance(seg, list):
+                    oracle.push(z, seg, ref)
+                elif use_sur:
+                    z = oracle.mlp_apply(sh, params[k], norms[k], z, mode=0)
+                    ref.gamma += seg.dE_MeV / ref.mass_MeV
+                    k += 1
+                else:
+                    oracle.push(z, [seg], ref)
+            return z
+        return track
 
-    def timed_track(z):
+    n_el = chain.n_elements()
+    legs = {}
+    legs["surrogate_chain_c5"] = cpu_leg(filler(wl), tracker(wl, True), budget_s, wl.bunch.n, T,
+                                         {"element_pushes": n_el})
+    # fine-step chain: a 1e6-particle subset on all threads, then linear
+    # extrapolation to the full bunch
+    sub = min(wl.bunch.n, 1_000_000)
+    run_f, make_f = tracker(wl, False), filler(wl)
+    z = make_f(64)
+    t0 = time.perf_counter()
+    run_f(z)
+    m1 = int(max(64, min(sub, 0.25 * budget_s * 64 / (time.perf_counter() - t0))))
+    z = make_f(m1)
+    t0 = time.perf_counter()
+    run_f(z)
+    serial_rate = m1 / (time.perf_counter() - t0)
+    from concurrent.futures import ThreadPoolExecutor
+    per = (sub + T - 1) // T
+    with ThreadPoolExecutor(max_workers=T) as ex:
+        chunks = list(ex.map(lambda i: make_f(min(per, sub - i), i), range(0, sub, per)))
         t0 = time.perf_counter()
-        track(z)
-        return time.perf_counter() - t0
-
-    t_small = timed_track(fill(256)) / 256
-    m1 = int(max(256, min(wl.bunch.n, 0.5 * budget_s / max(t_small, 1e-12))))
-    t1 = timed_track(fill(m1))
-    threads = max(1, min(16, os.cpu_count() or 1))
-    m2 = min(wl.bunch.n, m1 * threads)
-    per = (m2 + threads - 1) // threads
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        chunks = list(ex.map(lambda i: fill(min(per, m2 - i), i), range(0, m2, per)))
-        t0 = time.perf_counter()
-        list(ex.map(track, chunks))
-        t2 = time.perf_counter() - t0
-    return {"value": m2 / t2, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {m2} particles of the {wl.bunch.n}-particle bunch through the full staged "
-                      f"beamline (lattice gaps + 4 surrogate stages, FP64 network), {threads} threads over "
-                      f"particle ranges, {t2:.1f} s wall (fill excluded)",
-            "serial_value": m1 / t1, "serial_sample": f"first {m1} particles on one core, {t1:.1f} s"}
+        list(ex.map(run_f, chunks))
+        t_sub = time.perf_counter() - t0
+    legs["fine_step_chain_c5"] = {
+        "serial_particles_per_s": serial_rate, "serial_sample": m1,
+        "threads_particles_per_s": sub / t_sub, "threads_sample": sub, "threads_s": t_sub, "threads": T,
+        "full_bunch_extrapolated_threads_s": wl.bunch.n * t_sub / sub,
+        "full_bunch_extrapolated_serial_s": wl.bunch.n / serial_rate,
+        "note": f"measured on the first {sub} particles with {T} threads; the full-bunch times are "
+                f"linear extrapolations, not measurements"}
+    c3 = W.c3_stage()
+    legs["fine_step_stage_c3"] = cpu_leg(filler(c3), tracker(c3, False), budget_s / 2, c3.bunch.n, T,
+                                         {"substep_pushes": c3.beamline[1].nsub})
+    c3_net = W.c3_stage()
+    legs["surrogate_stage_fp64_network"] = cpu_leg(
+        filler(c3_net), lambda z: oracle.mlp_apply(sh, params[0], norms[0], z, mode=0), budget_s / 4,
+        W.C4_INFER_N, T)
+    legs["surrogate_stage_fp64_network"]["note"] = ("the oracle's FP64 network (6-64-64-64-6 tanh) on "
+                                                    "the C3 bunch: the cost of one surrogate stage")
+    c1 = W.c1_fodo()
+    legs["fodo_c1"] = cpu_leg(filler(c1), tracker(c1, False), budget_s / 8, c1.bunch.n, T,
+                              {"element_pushes": len(c1.beamline[0])})
+    c2 = W.c2_fused()
+    legs["lattice58_c2"] = cpu_leg(filler(c2), tracker(c2, False), budget_s / 4, c2.bunch.n, T,
+                                   {"element_pushes": len(c2.beamline[0])})
+    head = legs["surrogate_chain_c5"]
+    return {"value": head["threads_particles_per_s"], "unit": "particles/s", "cores": T, "kind": "oracle",
+            "sample": f"first {head['threads_sample']} particles of the {wl.bunch.n}-particle bunch through the "
+                      f"full staged beamline (lattice gaps + 4 surrogate stages, FP64 network), {T} threads "
+                      f"over particle ranges, {head['threads_s']:.1f} s wall (fill excluded)",
+            "serial_value": head["serial_particles_per_s"],
+            "serial_sample": f"first {head['serial_sample']} particles on one core, {head['serial_s']:.1f} s",
+            "host": host, "legs": legs}
 
 
 def single_stage_study(args, log, chromatic=False):
@@ -236,10 +347,18 @@ def single_stage_study(args, log, chromatic=False):
     sur = hbl.Surrogate(W.mlp_init_seed(0))
     t0 = time.perf_counter()
     curve = sur.train(zin, zout, npairs, batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR,
-                      lr_final=1e-5, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0))
+                      lr_final=1e-5, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0),
+                      keep_best=W.TRAIN_KEEP)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     sur.set_stage(stage, entry)
+    others = []                          # further init/shuffle seed sets on the same pairs
+    for sd in range(1, 1 if chromatic else args.seed_sets):
+        o = hbl.Surrogate(W.mlp_init_seed(0) + 1000 * sd)
+        o.train(zin, zout, npairs, batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR, lr_final=1e-5,
+                train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0) + 1000 * sd, keep_best=W.TRAIN_KEEP)
+        o.set_stage(stage, entry)
+        others.append((sd, o))
     del zin, zout
 
     N = W.C4_INFER_N
@@ -249,6 +368,12 @@ def single_stage_study(args, log, chromatic=False):
     s = x.clone()
     sur.apply(s, r0.copy(), n=N)
     rms, cen, eps = hbl.compare(s, f, n=N)
+    by_seed = {"0": eps}
+    for sd, o in others:
+        so = x.clone()
+        o.apply(so, r0.copy(), n=N)
+        by_seed[str(sd)] = hbl.compare(so, f, n=N)[2]
+        del so
     t_inf = time_events(torch, lambda: sur.apply(s, r0.copy(), n=N), 10)
     t_fine = time_events(torch, lambda: hbl.apply_stage(f, stage, r0.copy(), n=N), 3)
     del s, f
@@ -285,6 +410,8 @@ def single_stage_study(args, log, chromatic=False):
            "particles": N, "epochs": args.epochs,
            "train_seconds": t_train, "final_loss_train_test": [float(v) for v in curve[-1]],
            "eps_rel_xyt_vs_2000_substeps": eps, "rms_over_sigma": rms, "centroid_over_sigma": cen,
+           "eps_rel_xyt_by_seed_set": by_seed,
+           "max_abs_eps_rel_xy_over_seed_sets": max(max(abs(v[0]), abs(v[1])) for v in by_seed.values()),
            "inference_ms": t_inf * 1e3, "fine_step_2000_ms": t_fine * 1e3, "speedup_vs_2000": t_fine / t_inf,
            "eps_err_vs_converged_32000": {"surrogate": err_s, "fine_step_at_equal_error_nsub": n_eq},
            "fine_step_equal_error_ms": t_fine_eq * 1e3, "speedup_at_equal_error": t_fine_eq / t_inf,
@@ -603,6 +730,51 @@ def paper_shape_study(log):
     return out
 
 
+def stage_accuracy_study(args, log, wl, chain):
+    """Each chain stage's surrogate against its own fine-step map on the
+    chain's own inputs: the full bunch tracked with fine-step stages to the
+    stage entrance, then the stage (fine-step) and the surrogate applied to
+    the same particles.  The networks of the chain (seed set 0) and networks
+    trained with further init/shuffle seed sets on the same pairs give the
+    spread of the per-stage emittance error over seeds."""
+    import workloads as W
+    from paper_2402_17248_amd import hbl
+
+    n, sig = wl.bunch.n, wl.bunch.sigma
+    seeds = list(range(args.seed_sets))
+    out = []
+    for k in range(chain.stage_count):
+        zin, zout = chain.make_pairs(k, n, wl.bunch.seed, sig)
+        stage, entry = chain.stage(k), chain.entry_ref(k)
+        nets = {0: chain.surrogates[k]}
+        pin = pout = None
+        for sd in seeds[1:]:
+            if pin is None:
+                pin, pout = chain.make_pairs(k, args.pairs, W.c5_pair_seed(k + 1), sig)
+            sur = hbl.Surrogate(W.mlp_init_seed(k + 1) + 1000 * sd)
+            sur.train(pin, pout, args.pairs, batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR,
+                      lr_final=1e-5, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(k + 1) + 1000 * sd,
+                      keep_best=W.TRAIN_KEEP)
+            sur.set_stage(stage, entry)
+            nets[sd] = sur
+        del pin, pout
+        row = {"stage": k + 1, "particles": n, "by_seed_set": {}}
+        for sd, sur in nets.items():
+            zs = zin.clone()
+            sur.apply(zs, entry.copy(), n=n)
+            rms, cen, eps = hbl.compare(zs, zout, n=n)
+            del zs
+            row["by_seed_set"][str(sd)] = {"eps_rel_xyt": eps, "rms_over_sigma": rms, "centroid_over_sigma": cen}
+        worst = max(max(abs(v["eps_rel_xyt"][0]), abs(v["eps_rel_xyt"][1])) for v in row["by_seed_set"].values())
+        row["max_abs_eps_rel_xy_over_seed_sets"] = worst
+        log(f"stage {k + 1} surrogate vs its fine-step map on the chain's inputs: eps_rel x,y by seed set "
+            + ", ".join(f"{sd}: [{v['eps_rel_xyt'][0]:+.2e}, {v['eps_rel_xyt'][1]:+.2e}]"
+                        for sd, v in row["by_seed_set"].items()))
+        out.append(row)
+        del zin, zout, nets
+    return out
+
+
 def chain_equal_error(args, wl, chain, dt_sur, step_fn, log):
     """The staged chain at equal error: on the first 1e6 particles of the
     benchmark bunch, the emittance error of the surrogate chain and of the
@@ -699,6 +871,7 @@ def main():
     # ---- train the four stage surrogates on the GPU (not timed as the metric)
     t0 = time.perf_counter()
     curves = chain.train_surrogates(args.pairs, sig, W.c5_pair_seed, W.mlp_init_seed, W.shuffle_seed,
+                                    keep_best=W.TRAIN_KEEP,
                                     epochs=args.epochs, batch=W.TRAIN_BATCH, lr=W.TRAIN_LR, lr_final=1e-5,
                                     train_frac=W.TRAIN_FRAC, log=log)
     torch.cuda.synchronize()
@@ -784,8 +957,9 @@ def main():
     del zs
     z_fine = z.clone()                  # the fine-step chain's result, kept for the paper-shaped chain
 
-    equal = configs = None
+    equal = configs = per_stage = None
     if not args.no_single_stage:
+        per_stage = stage_accuracy_study(args, log, wl, chain)
         equal = chain_equal_error(args, wl, chain, dt_sur, time_chain, log)
         configs = config_studies(log)
 
@@ -810,7 +984,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, chain, args.cpu_seconds)
-        log(f"cpu oracle: {cpu['value']:.4g} particles/s ({cpu['sample']})")
+        log(f"cpu oracle: {cpu['value']:.4g} particles/s ({cpu['sample']}); host {cpu['host']}")
+        for k, v in cpu["legs"].items():
+            log(f"cpu oracle leg {k}: serial {v['serial_particles_per_s']:.4g}, {v['threads']} threads "
+                f"{v['threads_particles_per_s']:.4g} particles/s")
 
     line = {
         "metric": "particles/s through staged beamline: surrogate vs fine-step stage, same error",
@@ -827,7 +1004,7 @@ def main():
         "fine_step_path": {"value": n / dt_fine, "ms_per_step": dt_fine * 1e3, "nsub": chain.stage(0).nsub,
                            "speedup_surrogate": dt_fine / dt_sur},
         "accuracy_vs_fine_step": {"eps_rel_xyt": eps_rel, "rms_over_sigma": rms,
-                                  "centroid_over_sigma": cen},
+                                  "centroid_over_sigma": cen, "per_stage": per_stage},
         "step_breakdown_ms": breakdown,
         "stage_pass_kernels": {"inference_ms": t_inf * 1e3, "fine_step_ms": t_fs * 1e3,
                                "speedup": t_fs / t_inf, "launches_per_step": n_pass,

@@ -242,7 +242,17 @@ typedef struct hbl_mlp_shape {
  * round(train_frac * n_pairs) pairs train, the rest test (§3: 70/30); each
  * epoch visits the training pairs in a Fisher-Yates order (Philox4x32-10,
  * key shuffle_seed, counter (i/4, epoch, 'SHUF'), word i%4, j = floor(r (i+1)
- * / 2^32)) in batches, dropping the last partial batch. */
+ * / 2^32)) in batches, dropping the last partial batch.  keep_best selects,
+ * when there is a test split, which epoch's parameters the training ends
+ * with (model selection on the held-out pairs, tracked on the device with no
+ * host synchronisation per epoch; the Adam moments and step stay those of the
+ * last step): 0, the last epoch's; 1, those of the lowest test loss; 2, among
+ * the epochs of the last quarter (at least the last) whose test loss is
+ * within 10 % of the lowest test loss of those epochs, those whose predicted
+ * test outputs have the emittances of (x, px) and (y, py) (§4) closest to
+ * those of the true test outputs (the lowest max over the two planes of
+ * |eps_pred / eps_true - 1|; keeps a 36.6 KB parameter snapshot per epoch of
+ * that quarter in device memory during the call).  reserved must be 0. */
 typedef struct hbl_train_cfg {
     int32_t batch;
     int32_t epochs;
@@ -250,6 +260,8 @@ typedef struct hbl_train_cfg {
     float lr, lr_final, beta1, beta2, eps;
     double train_frac;
     uint64_t shuffle_seed;
+    int32_t keep_best;
+    int32_t reserved;
 } hbl_train_cfg;
 
 /* Create a surrogate with parameters U(-1/sqrt(fan_in), 1/sqrt(fan_in)):
@@ -377,7 +389,8 @@ hbl_status hbl_prelu_loss_grad(hbl_prelu_net* m, const double* zin, const double
 /* Train as hbl_surrogate_train (normalisation from the training split, Adam
  * reset, half-cosine learning rate, Fisher-Yates epoch order, test loss per
  * epoch), entirely on the device; batch any size in [1, 16384] (§4.2 uses
- * 1200).  SYNC at the end; loss_log as for hbl_surrogate_train. */
+ * 1200).  cfg->keep_best must be 0 here (HBL_EINVAL otherwise).  SYNC at the
+ * end; loss_log as for hbl_surrogate_train. */
 hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zout, int64_t n_pairs,
                            int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream);
 

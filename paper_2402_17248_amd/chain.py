@@ -60,16 +60,18 @@ class Chain:
         return zin, zout
 
     def train_surrogates(self, n_pairs: int, sigma, pair_seed, init_seed, shuffle_seed, epochs: int,
-                         batch=4096, lr=1e-3, lr_final=1e-5, train_frac=0.7, stages=None, log=None):
+                         batch=4096, lr=1e-3, lr_final=1e-5, train_frac=0.7, stages=None, log=None,
+                         keep_best=False):
         """Train one surrogate per stage, each on its own pairs (the paper
         trains one network per stage, §4.2).  Seeds are callables of the
-        1-based stage number."""
+        1-based stage number.  keep_best: each network ends with the
+        parameters of its lowest test loss."""
         logs = []
         for k in (range(self.stage_count) if stages is None else stages):
             zin, zout = self.make_pairs(k, n_pairs, pair_seed(k + 1), sigma)
             sur = hbl.Surrogate(init_seed(k + 1))
             curve = sur.train(zin, zout, n_pairs, batch=batch, epochs=epochs, lr=lr, lr_final=lr_final,
-                              train_frac=train_frac, shuffle_seed=shuffle_seed(k + 1))
+                              train_frac=train_frac, shuffle_seed=shuffle_seed(k + 1), keep_best=keep_best)
             sur.set_stage(self.stage(k), self.entry_ref(k))
             self.surrogates[k] = sur
             logs.append(curve)

@@ -811,6 +811,9 @@ void epoch_order(int32_t* perm, int64_t n, uint64_t seed, int64_t epoch) {
 }
 
 constexpr int kMlpParams = 9158;
+// keep_best = 2: candidates are the window epochs whose test loss is within
+// this fraction of the window's lowest
+constexpr double kEpsSelectLossTol = 0.10;
 constexpr uint64_t kFileMagic = 0x31534C42484C4248ull;  // "HBLHBLS1"
 
 }  // namespace
@@ -832,6 +835,8 @@ struct hbl_surrogate {
     float* d_loss_part;
     double* d_eval_part;
     double* d_loss_acc;
+    float* d_best;          // parameters of the lowest test loss (keep_best)
+    double* d_best_info;    // {lowest test loss, its epoch}
     int32_t part_blocks;
     int32_t loss_slots;
 };
@@ -840,7 +845,8 @@ namespace {
 
 void sur_free(hbl_surrogate* m) {
     if (!m) return;
-    void* ptrs[] = {m->d_params, m->d_m, m->d_v, m->d_img, m->d_part, m->d_loss_part, m->d_eval_part, m->d_loss_acc};
+    void* ptrs[] = {m->d_params, m->d_m,         m->d_v,          m->d_img,   m->d_part,
+                    m->d_loss_part, m->d_eval_part, m->d_loss_acc, m->d_best, m->d_best_info};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete m;
@@ -1137,6 +1143,8 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
     HBL_REQUIRE(isfinite(cfg->eps) && cfg->eps > 0, "surrogate_train: eps must be > 0");
     HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "surrogate_train: train_frac must be in (0, 1]");
     HBL_REQUIRE(n_pairs <= INT32_MAX, "surrogate_train: at most 2^31-1 pairs");
+    HBL_REQUIRE(cfg->keep_best >= 0 && cfg->keep_best <= 2, "surrogate_train: keep_best must be 0, 1 or 2");
+    HBL_REQUIRE(cfg->reserved == 0, "surrogate_train: reserved must be 0");
     const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
     const int64_t n_test = n_pairs - n_train;
     HBL_REQUIRE(n_train >= cfg->batch, "surrogate_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);
@@ -1164,6 +1172,16 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
     const int32_t nb = cfg->batch / 64;
     const int64_t steps_per_epoch = n_train / cfg->batch;
     if (hbl_status st = ensure_train_scratch(m, nb, 2 * (cfg->epochs > 0 ? cfg->epochs : 1))) return st;
+    const bool keep_best = cfg->keep_best && n_test > 0 && cfg->epochs > 0;
+    const bool by_eps = keep_best && cfg->keep_best == 2;
+    if (keep_best && !m->d_best) {
+        if (hipMalloc((void**)&m->d_best, sizeof(float) * kMlpParams) != hipSuccess ||
+            hipMalloc((void**)&m->d_best_info, 2 * sizeof(double)) != hipSuccess) {
+            set_error(HBL_ENOMEM, "surrogate_train: best-parameter buffer allocation failed");
+            return HBL_ENOMEM;
+        }
+    }
+    if (keep_best) HBL_HIP(launch_best_init(m->d_best_info, s));
     // fresh Adam state
     HBL_HIP(hipMemsetAsync(m->d_m, 0, sizeof(float) * kMlpParams, s));
     HBL_HIP(hipMemsetAsync(m->d_v, 0, sizeof(float) * kMlpParams, s));
@@ -1184,6 +1202,31 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
         if (e == hipSuccess) e = hipMalloc((void**)&d_perm[k], sizeof(int32_t) * n_train);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
         if (e != hipSuccess) fail(HBL_ENOMEM, "order buffers", e);
+    }
+    // emittance criterion: predictions of the test split in a bunch of their
+    // own; the true test outputs' moments once; after each epoch of the
+    // window (the last quarter of the epochs, at least the last) the
+    // predictions' moments, a parameter snapshot and its {score, test loss}
+    double* d_pred = nullptr;
+    double* d_mom = nullptr;   // [0, 27): true test outputs, [32, 59): predictions
+    double* d_ws = nullptr;
+    float* d_snap = nullptr;
+    double* d_rec = nullptr;
+    const int64_t ld_pred = n_test + (n_test & 1);
+    const int64_t n_win = cfg->epochs / 4 > 0 ? cfg->epochs / 4 : 1;
+    const int64_t eps_from = cfg->epochs - n_win;
+    if (by_eps && st == HBL_OK) {
+        hipError_t e = hipMalloc((void**)&d_pred, sizeof(double) * 6 * (size_t)ld_pred);
+        if (e == hipSuccess) e = hipMalloc((void**)&d_mom, sizeof(double) * 64);
+        if (e == hipSuccess) e = hipMalloc((void**)&d_ws, reduce_ws_bytes(n_test));
+        if (e == hipSuccess) e = hipMalloc((void**)&d_snap, sizeof(float) * kMlpParams * (size_t)n_win);
+        if (e == hipSuccess) e = hipMalloc((void**)&d_rec, sizeof(double) * 2 * (size_t)n_win);
+        if (e != hipSuccess) {
+            fail(HBL_ENOMEM, "test-prediction buffers", e);
+        } else {
+            e = launch_moments(zout + n_train, n_test, ld, d_ws, d_mom, s);
+            if (e != hipSuccess) fail(HBL_EHIP, "test-split moments", e);
+        }
     }
     std::vector<int64_t> steps_done(cfg->epochs > 0 ? cfg->epochs : 1, 0);
     int64_t planned = (int64_t)cfg->epochs * steps_per_epoch;
@@ -1218,8 +1261,28 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
         if (n_test > 0) {
             e = launch_eval_loss(zin, zout, ld, n_train, n_test, m->d_img, m->norm, m->d_eval_part,
                                  m->d_loss_acc + 2 * ep + 1, s);
+            if (e == hipSuccess && keep_best && !by_eps)
+                e = launch_keep_best(m->d_loss_acc + 2 * ep + 1, m->d_best_info, m->d_params, m->d_best, ep, s);
+            if (e == hipSuccess && by_eps && ep >= eps_from) {
+                e = hipMemcpy2DAsync(d_pred, sizeof(double) * ld_pred, zin + n_train, sizeof(double) * ld,
+                                     sizeof(double) * n_test, 6, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess)
+                    e = launch_mlp_infer(d_pred, n_test, ld_pred, m->d_img, m->norm, view_of(nullptr),
+                                         view_of(nullptr), s);
+                if (e == hipSuccess) e = launch_moments(d_pred, n_test, ld_pred, d_ws, d_mom + 32, s);
+                if (e == hipSuccess)
+                    e = launch_snapshot(d_mom + 32, d_mom, m->d_loss_acc + 2 * ep + 1, m->d_params,
+                                        d_snap + (ep - eps_from) * kMlpParams, d_rec + 2 * (ep - eps_from), s);
+            }
             if (e != hipSuccess) { fail(HBL_EHIP, "test loss launch", e); break; }
         }
+    }
+    if (st == HBL_OK && keep_best) {
+        hipError_t e2 = by_eps ? launch_select_snapshot(d_rec, (int)n_win, kEpsSelectLossTol, d_snap, m->d_params,
+                                                        m->d_best_info, s)
+                               : launch_restore_best(m->d_best_info, m->d_best, m->d_params, s);
+        if (e2 == hipSuccess) e2 = launch_mlp_pack(m->d_params, m->d_img, s);
+        if (e2 != hipSuccess) fail(HBL_EHIP, "best-parameter restore", e2);
     }
     hipError_t e = hipStreamSynchronize(s);
     if (st == HBL_OK && e != hipSuccess) fail(HBL_EHIP, "training", e);
@@ -1237,6 +1300,9 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
         if (d_perm[k]) (void)hipFree(d_perm[k]);
         if (h_perm[k]) (void)hipHostFree(h_perm[k]);
     }
+    void* scratch_bufs[] = {d_pred, d_mom, d_ws, d_snap, d_rec};
+    for (void* q : scratch_bufs)
+        if (q) (void)hipFree(q);
     return st;
 }
 
@@ -1779,6 +1845,8 @@ hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zo
     HBL_REQUIRE(isfinite(cfg->eps) && cfg->eps > 0, "prelu_train: eps must be > 0");
     HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "prelu_train: train_frac must be in (0, 1]");
     HBL_REQUIRE(n_pairs <= INT32_MAX, "prelu_train: at most 2^31-1 pairs");
+    HBL_REQUIRE(cfg->keep_best == 0 && cfg->reserved == 0,
+                "prelu_train: keep_best is not supported by the paper-shaped network (must be 0)");
     const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
     const int64_t n_test = n_pairs - n_train;
     HBL_REQUIRE(n_train >= cfg->batch, "prelu_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);

@@ -101,6 +101,17 @@ hipError_t launch_diff2(const double* zs, const double* zf, int64_t n, int64_t l
 int mlp_nparams();
 int mlp_image_words();
 hipError_t launch_mlp_pack(const float* params, uint32_t* img, hipStream_t s);
+// Lowest-test-loss parameter copy (info: 2 doubles, best: mlp_nparams() floats).
+hipError_t launch_best_init(double* info, hipStream_t s);
+hipError_t launch_keep_best(const double* loss, double* info, const float* params, float* best, int64_t epoch,
+                            hipStream_t s);
+// Emittance criterion: snapshot the parameters with {score, test loss} into
+// rec (2 doubles), then select among nw snapshots and restore the choice.
+hipError_t launch_snapshot(const double* pred27, const double* true27, const double* loss, const float* params,
+                           float* snap, double* rec, hipStream_t s);
+hipError_t launch_select_snapshot(const double* rec, int nw, double tol, const float* snap, float* params,
+                                  double* info, hipStream_t s);
+hipError_t launch_restore_best(const double* info, const float* best, float* params, hipStream_t s);
 hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* img, const double* norm24,
                             const LatticeView& pre, const LatticeView& post, hipStream_t s);
 hipError_t launch_train_step(const double* zin, const double* zout, int64_t ld, const int32_t* idx,

@@ -666,9 +666,124 @@ __global__ void k_sum_scaled(const double* part, int nb, double scale, double* o
     }
 }
 
+// Model selection on the test split: after each epoch's test loss, keep a
+// copy of the parameters when the loss is the lowest so far (info = {lowest
+// test loss, its epoch}); at the end, restore the copy.  One block each.
+__global__ void k_best_init(double* info) {
+    if (threadIdx.x == 0) {
+        info[0] = __builtin_huge_val();
+        info[1] = -1.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_keep_best(const double* __restrict__ loss, double* __restrict__ info,
+                                                   const float* __restrict__ p, float* __restrict__ best,
+                                                   double epoch) {
+    const double l = *loss;
+    const bool better = l < info[0];   // a NaN loss is never better; uniform over the block
+    __syncthreads();                   // every thread has read info[0] before it changes
+    if (!better) return;
+    for (int i = threadIdx.x; i < kNParams; i += 256) best[i] = p[i];
+    if (threadIdx.x == 0) {
+        info[0] = l;
+        info[1] = epoch;
+    }
+}
+
+// Emittance criterion: after each epoch of the selection window the
+// parameters are kept as a snapshot, with the epoch's test loss and score:
+// the test split's predicted and true moments (27 values each: 6 means, then
+// the 21 upper-triangle covariances) give the emittances of (x, px) and
+// (y, py) (Kahan's FMA product difference), and the score is the larger of
+// |eps_pred / eps_true - 1| over the two planes.  At the end the snapshot of
+// the lowest score among the epochs whose test loss is within a factor
+// (1 + tol) of the window's lowest is restored.
+__device__ __forceinline__ double plane_emittance(const double* m27, int j) {
+    const int k = j + 3;
+    const double a = m27[6 + j * 6 - j * (j - 1) / 2];
+    const double b = m27[6 + j * 6 - j * (j - 1) / 2 + (k - j)];
+    const double d = m27[6 + k * 6 - k * (k - 1) / 2];
+    const double w = b * b;
+    const double det = fma(a, d, -w) + fma(-b, b, w);
+    return det > 0.0 ? sqrt(det) : 0.0;
+}
+
+// snapshot w of the window: parameters, then {score, test loss}
+__global__ __launch_bounds__(256) void k_snapshot(const double* __restrict__ pred27, const double* __restrict__ true27,
+                                                  const double* __restrict__ loss, const float* __restrict__ p,
+                                                  float* __restrict__ snap, double* __restrict__ rec) {
+    for (int i = threadIdx.x; i < kNParams; i += 256) snap[i] = p[i];
+    if (threadIdx.x == 0) {
+        double score = 0.0;
+        for (int j = 0; j < 2; ++j)
+            score = fmax(score, fabs(plane_emittance(pred27, j) / plane_emittance(true27, j) - 1.0));
+        rec[0] = isnan(score) ? __builtin_huge_val() : score;
+        rec[1] = isnan(*loss) ? __builtin_huge_val() : *loss;
+    }
+}
+
+// choose among nw snapshots (records rec[2w], rec[2w + 1]) and restore it;
+// info = {score, window index} of the choice
+__global__ __launch_bounds__(256) void k_select_snapshot(const double* __restrict__ rec, int nw, double tol,
+                                                         const float* __restrict__ snap, float* __restrict__ p,
+                                                         double* __restrict__ info) {
+    __shared__ int pick;
+    if (threadIdx.x == 0) {
+        double lo = __builtin_huge_val();
+        for (int w = 0; w < nw; ++w) lo = fmin(lo, rec[2 * w + 1]);
+        int best = nw - 1;
+        double bs = __builtin_huge_val();
+        for (int w = 0; w < nw; ++w)
+            if (rec[2 * w + 1] <= (1.0 + tol) * lo && rec[2 * w] < bs) {
+                bs = rec[2 * w];
+                best = w;
+            }
+        pick = best;
+        info[0] = bs;
+        info[1] = (double)best;
+    }
+    __syncthreads();
+    const float* src = snap + (int64_t)pick * kNParams;
+    for (int i = threadIdx.x; i < kNParams; i += 256) p[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_restore_best(const double* __restrict__ info,
+                                                      const float* __restrict__ best, float* __restrict__ p) {
+    if (info[1] < 0.0) return;
+    for (int i = threadIdx.x; i < kNParams; i += 256) p[i] = best[i];
+}
+
 }  // namespace
 
 int mlp_nparams() { return kNParams; }
+
+hipError_t launch_best_init(double* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_best_init, dim3(1), dim3(64), 0, s, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_keep_best(const double* loss, double* info, const float* params, float* best, int64_t epoch,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_keep_best, dim3(1), dim3(256), 0, s, loss, info, params, best, (double)epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const double* pred27, const double* true27, const double* loss, const float* params,
+                           float* snap, double* rec, hipStream_t s) {
+    hipLaunchKernelGGL(k_snapshot, dim3(1), dim3(256), 0, s, pred27, true27, loss, params, snap, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_snapshot(const double* rec, int nw, double tol, const float* snap, float* params,
+                                  double* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_snapshot, dim3(1), dim3(256), 0, s, rec, nw, tol, snap, params, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_restore_best(const double* info, const float* best, float* params, hipStream_t s) {
+    hipLaunchKernelGGL(k_restore_best, dim3(1), dim3(256), 0, s, info, best, params);
+    return hipGetLastError();
+}
 int mlp_image_words() { return kImgWords * 64; }
 
 hipError_t launch_mlp_pack(const float* params, uint32_t* img, hipStream_t s) {

@@ -98,12 +98,15 @@ def chain_emittances(wl, z0, n: int, apply_stage: Callable) -> List[float]:
 
 def train_stage_surrogate(wl_of_lenses: Callable, k: int, lens_sets: Sequence[Sequence[Tuple[float, float]]],
                           n_pairs: int, pair_seed: int, init_seed: int, shuffle_seed: int, epochs: int,
-                          batch: int = 4096, lr: float = 1e-3, lr_final: float = 1e-5, log=None):
+                          batch: int = 4096, lr: float = 1e-3, lr_final: float = 1e-5, log=None,
+                          keep_best: int = 1):
     """A surrogate of stage k (0-based) trained on pairs pooled over several
     chain configurations (lens_sets: the three interstage lenses of each), so
     that the inputs an optimiser produces stay inside the training
     distribution (the paper's widened training set, §4.2).  n_pairs split
-    evenly over the configurations; the fine-step map produces the pairs."""
+    evenly over the configurations; the fine-step map produces the pairs.
+    keep_best as in hbl_train_cfg (default: the lowest test loss, since the
+    test split mixes the configurations)."""
     import torch
 
     from .chain import Chain
@@ -125,7 +128,7 @@ def train_stage_surrogate(wl_of_lenses: Callable, k: int, lens_sets: Sequence[Se
     zout[:, :tot] = zout[:, idx]
     sur = hbl.Surrogate(init_seed)
     curve = sur.train(zin, zout, tot, batch=batch, epochs=epochs, lr=lr, lr_final=lr_final,
-                      shuffle_seed=shuffle_seed)
+                      shuffle_seed=shuffle_seed, keep_best=keep_best)
     wl = wl_of_lenses(list(lens_sets[0]))
     chain = Chain(wl.beamline, wl.E_MeV)
     sur.set_stage(chain.stage(k), chain.entry_ref(k))

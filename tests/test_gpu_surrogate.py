@@ -288,3 +288,68 @@ def test_apply_moves_reference_and_checks_entry(hbl, orc, pairs):
     with pytest.raises(hbl.HblError) as ei:
         s.apply(rec.clone(), bad, n=n)
     assert ei.value.status == hbl.HBL_EINVAL
+
+
+def test_keep_best_restores_lowest_test_loss_epoch(hbl, orc, pairs):
+    """keep_best ends with the parameters after the epoch of lowest test loss:
+    with a constant learning rate (the schedule then does not depend on the
+    epoch count) and deterministic training, they equal bit for bit those of
+    a second run from the same start stopped right after that epoch, and a
+    run without keep_best ends with the last epoch's parameters."""
+    n, rec, out, _, _, _, _ = pairs
+    cfg = dict(batch=256, epochs=10, lr=5e-3, shuffle_seed=9)
+    a = hbl.Surrogate(21)
+    log = a.train(rec, out, n, keep_best=True, **cfg)
+    best = int(np.argmin(log[:, 1]))
+    print(f"keep_best: test losses {log[:, 1].tolist()}, lowest after epoch {best}", flush=True)
+    b = hbl.Surrogate(21)
+    log_b = b.train(rec, out, n, **{**cfg, "epochs": best + 1})
+    assert np.array_equal(log_b, log[: best + 1])
+    assert np.array_equal(a.get_params(), b.get_params())
+    c = hbl.Surrogate(21)
+    log_c = c.train(rec, out, n, **cfg)
+    assert np.array_equal(log_c, log)
+    if best < cfg["epochs"] - 1:
+        assert not np.array_equal(c.get_params(), a.get_params())
+
+
+def test_keep_best_by_test_split_emittance(hbl, orc, pairs):
+    """keep_best=2 ends with the parameters, among the epochs of the last
+    quarter whose test loss is within 10 % of those epochs' lowest, whose
+    predicted test outputs have the emittances of (x, px) and (y, py) closest
+    to the true test outputs'.  With a constant rate the candidates are the
+    parameters of runs stopped after each of those epochs: the kept
+    parameters equal, bit for bit, those of the eligible candidate with the
+    lowest max_p |eps_pred,p / eps_true,p - 1| on the test split (computed
+    here through hbl_compare)."""
+    import torch
+    n, rec, out, _, _, stage, entry = pairs
+    cfg = dict(batch=256, epochs=16, lr=5e-3, shuffle_seed=13)
+    ntr = int(round(0.7 * n))
+    nte = n - ntr
+    tin, tout = hbl.new_bunch(nte), hbl.new_bunch(nte)
+    tin[:, :nte] = rec[:, ntr:n]
+    tout[:, :nte] = out[:, ntr:n]
+    a = hbl.Surrogate(31)
+    log = a.train(rec, out, n, keep_best=2, **cfg)
+    first = cfg["epochs"] - cfg["epochs"] // 4
+    losses = log[first:, 1].astype(np.float64)
+    scores, params = [], []
+    for ep in range(first, cfg["epochs"]):
+        b = hbl.Surrogate(31)
+        b.train(rec, out, n, **{**cfg, "epochs": ep + 1})
+        b.set_stage(stage, entry)
+        zs = tin.clone()
+        b.apply(zs, entry.copy(), n=nte)
+        torch.cuda.synchronize()
+        _, _, e = hbl.compare(zs, tout, n=nte)
+        scores.append(max(abs(e[0]), abs(e[1])))
+        params.append(b.get_params())
+    ok = losses <= 1.1 * losses.min()
+    cand = np.where(ok, scores, np.inf)
+    k = int(np.argmin(cand))
+    print(f"keep_best=2: last-quarter test losses {losses.tolist()}, emittance scores {scores}; kept {k}",
+          flush=True)
+    srt = sorted(cand)
+    assert len(srt) < 2 or not np.isfinite(srt[1]) or srt[1] - srt[0] > 1e-12 * srt[1]   # a clear winner
+    assert np.array_equal(a.get_params(), params[k])

@@ -226,6 +226,11 @@ MLP_SHAPE = (6, 64, 3, 6)          # n_in, width, hidden layers, n_out
 TRAIN_BATCH = 4096
 TRAIN_LR = 1e-3
 TRAIN_FRAC = 0.7
+# Model selection on the 30 % test split: among the last quarter of the epochs
+# whose test loss is within 10 % of the lowest, the parameters whose predicted
+# test outputs have the x and y emittances closest to the true ones
+# (hbl_train_cfg.keep_best = 2).
+TRAIN_KEEP = 2
 ADAM_BETAS = (0.9, 0.999)
 ADAM_EPS = 1e-8
 
