@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--epochs", type=int, default=1200, help="training epochs per surrogate")
     ap.add_argument("--pairs", type=int, default=1 << 20)
     ap.add_argument("--lens-epochs", type=int, default=300, help="training epochs of the lens-chain surrogates")
+    ap.add_argument("--lens-refine", type=int, default=2,
+                    help="trust-region rounds per interstage of the lens optimisation (retrain + local search)")
+    ap.add_argument("--only-lens", action="store_true", help="run only the lens-optimisation study")
     ap.add_argument("--prelu-epochs", type=int, default=60,
                     help="epochs of the paper-shaped 3 x 700 surrogate trained with the paper's recipe")
     ap.add_argument("--fine-steps", type=int, default=2, help="timed steps of the fine-step path")
@@ -492,61 +495,37 @@ def lens_optimisation_study(args, log):
     optimised stage by stage for the horizontal emittance after the next
     stage, with the stages taken by surrogates; the surrogate of the next
     stage is trained just before each lens is optimised, on pairs pooled over
-    eight settings of that lens in the search box.  The lenses found are then
+    eight settings of that lens in the search box, then retrained around the
+    lens found in each trust-region round.  The lenses found are then
     checked with the fine-step stages (full fidelity), against the starting
-    lenses."""
-    import numpy as np
-    import torch
-
+    lenses, and the surrogate chain's emittances against that check."""
     import workloads as W
     from paper_2402_17248_amd import hbl
-    from paper_2402_17248_amd.optimize import (chain_emittances, chain_with_moment_lenses, optimise_lenses,
-                                                train_stage_surrogate)
+    from paper_2402_17248_amd.optimize import (chain_emittances, chain_with_moment_lenses,
+                                                optimise_lenses_on_surrogates)
 
-    # stage k + 1's surrogate is trained just before lens k is optimised, on pairs
-    # pooled over the start and seven seeded settings of lens k in the search box
-    # (the lenses before it fixed at the values found): the optimiser's inputs
     box = ((2.0, 7.0), (1.6, 4.0))
-    rng = np.random.default_rng(7)
-    settings = [W.LENS_START] + [(float(p), float(f)) for p, f in
-                                 zip(rng.uniform(*box[0], 7), rng.uniform(*box[1], 7))]
     wl_of = lambda lenses, n=1_000_000: W.c5_lens_chain(lenses, n=n)
-    t_train = 0.0
-    surs = [None] * 4
-
-    def train(k, lens_sets):
-        nonlocal t_train
-        t0 = time.perf_counter()
-        surs[k] = train_stage_surrogate(wl_of, k, lens_sets, 1 << 20, 300 + k, W.mlp_init_seed(k + 1),
-                                        W.shuffle_seed(k + 1), epochs=args.lens_epochs, log=log)
-        torch.cuda.synchronize()
-        t_train += time.perf_counter() - t0
-
-    def before_interstage(k, lenses):
-        rest = [W.LENS_START] * (2 - k)
-        train(k + 1, [lenses[:k] + [s] + rest for s in settings])
-
-    train(0, [[W.LENS_START] * 3])
     m = 1 << 17
     wl = wl_of([W.LENS_START] * 3, m)
     z0 = hbl.new_bunch(m)
     hbl.fill_gaussian(z0, wl.bunch.seed, (0.0,) * 6, wl.bunch.sigma, n=m)
-
-    def apply_sur(k, z, ref, pre, n):
-        surs[k].apply(z, ref, n=n, pre=pre)
-
     stages = [hbl.element(seg) for seg in wl.beamline if not isinstance(seg, list)]
 
     def apply_fine(k, z, ref, pre, n):
         hbl.apply_stage(z, stages[k], ref, n=n, pre=pre)
 
-    t_train0 = t_train
     t0 = time.perf_counter()
-    lenses, eps_opt, report = optimise_lenses(wl_of, W.LENS_START, z0, m, apply_sur,
-                                              bounds=box, max_evals=200, log=log,
-                                              before_interstage=before_interstage)
-    t_opt = time.perf_counter() - t0 - t_train + t_train0
+    lenses, eps_opt, report, surs, training_sets, t_train = optimise_lenses_on_surrogates(
+        wl_of, W.LENS_START, z0, m, box, 1 << 20, args.lens_epochs, lambda k: 300 + k,
+        lambda k: W.mlp_init_seed(k + 1), lambda k: W.shuffle_seed(k + 1),
+        refine_rounds=args.lens_refine, log=log)
+    t_opt = time.perf_counter() - t0 - t_train
     evals = sum(r["evaluations"] for r in report)
+
+    def apply_sur(k, z, ref, pre, n):
+        surs[k].apply(z, ref, n=n, pre=pre)
+
     N = 1_000_000
     zf = hbl.new_bunch(N)
     hbl.fill_gaussian(zf, 55, (0.0,) * 6, wl.bunch.sigma, n=N)
@@ -565,10 +544,12 @@ def lens_optimisation_study(args, log):
         f"(surrogate chain {['%.3e' % v for v in sur_opt]}); moment-driven centred lenses "
         f"{['%.3e' % v for v in fine_mom]}")
     return {"lenses_start": [W.LENS_START] * 3, "lenses_found": lenses, "training_seconds": t_train,
-            "training_lens_settings": settings, "evaluations": evals, "optimisation_seconds": t_opt,
+            "training_lens_settings": training_sets, "evaluations": evals, "optimisation_seconds": t_opt,
             "evaluations_per_s": evals / t_opt, "sample_particles": m, "check_particles": N,
             "eps_nx_fine_step_start": fine_start, "eps_nx_fine_step_optimised": fine_opt,
-            "eps_nx_surrogate_optimised": sur_opt, "per_interstage": report,
+            "eps_nx_surrogate_optimised": sur_opt,
+            "surrogate_prediction_rel_error": [a / b - 1 for a, b in zip(sur_opt, fine_opt)],
+            "refine_rounds": args.lens_refine, "per_interstage": report,
             "moment_driven_lenses": mom_lenses, "eps_nx_fine_step_moment_driven": fine_mom}
 
 
@@ -841,6 +822,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"other_configs": config_studies(log)}), flush=True)
+        return
+    if args.only_lens:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"lens_optimisation": lens_optimisation_study(args, log)}), flush=True)
         return
     if args.only_paper_shapes:
         import torch

@@ -24,7 +24,9 @@ def optimise_lenses(wl_of_lenses: Callable[[Sequence[Tuple[float, float]]], obje
                     apply_stage: Callable, bounds: Tuple[Tuple[float, float], Tuple[float, float]],
                     # bounds: ((position min, max), (focal length min, max))
                     max_evals: int = 200, xatol: float = 1e-3, fatol_rel: float = 1e-5, log=None,
-                    before_interstage: Optional[Callable[[int, list], None]] = None):
+                    before_interstage: Optional[Callable[[int, list], None]] = None,
+                    refine_rounds: int = 0, refine: Optional[Callable[[int, list, tuple], None]] = None,
+                    shrink: float = 4.0):
     """Optimise the three interstage lenses one after another.
 
     wl_of_lenses(lenses) -> workload whose beamline is [T, S1, I1, S2, I2, S3, I3, S4, T];
@@ -33,8 +35,13 @@ def optimise_lenses(wl_of_lenses: Callable[[Sequence[Tuple[float, float]]], obje
     with the lattice `pre_lattice` fused before it (None for none), ref moved.
     before_interstage(k, lenses), if given, runs before lens k is optimised
     (lenses 0..k-1 final), e.g. to train the model of stage k + 1 around the
-    current design.  Returns the lenses found, the horizontal emittance after
-    each stage, the evaluation count and the wall time per interstage."""
+    current design.  Trust-region refinement: after the search over `bounds`,
+    refine_rounds times the box shrinks by `shrink` around the lens found
+    (clipped to `bounds`), refine(k, lenses, box) runs (e.g. to retrain the
+    model of stage k + 1 on settings inside the box, where the optimum lies)
+    and the search restarts from the lens found, inside the box.  Returns the
+    lenses found, the horizontal emittance after each stage, and per
+    interstage the evaluation count and wall time."""
     import numpy as np
     from scipy.optimize import minimize
 
@@ -45,43 +52,124 @@ def optimise_lenses(wl_of_lenses: Callable[[Sequence[Tuple[float, float]]], obje
     apply_stage(0, z, ref, hbl.Lattice(wl.beamline[0], ref), n)       # entrance triplet + stage 1
     eps = [emittance_x(z, n)]
     report = []
+    (P_lo, P_hi), (F_lo, F_hi) = bounds
     for k in range(3):
         if before_interstage is not None:
             before_interstage(k, list(lenses))
         ref_k = ref.copy()
-        (p_lo, p_hi), (f_lo, f_hi) = bounds
         evals = 0
 
-        def objective(v):
-            nonlocal evals
-            p, f = float(v[0]), float(v[1])
-            if not (p_lo <= p <= p_hi and f_lo <= f <= f_hi):
-                return 1e30                     # outside the lens's travel / strength range
-            evals += 1
-            trial = list(lenses)
-            trial[k] = (p, f)
-            gap = wl_of_lenses(trial).beamline[2 + 2 * k]
-            r = ref_k.copy()
-            w = z.clone()
-            apply_stage(k + 1, w, r, hbl.Lattice(gap, r), n)
-            return emittance_x(w, n)
+        def search(box, x0, steps):
+            (p_lo, p_hi), (f_lo, f_hi) = box
+
+            def objective(v):
+                nonlocal evals
+                p, f = float(v[0]), float(v[1])
+                if not (p_lo <= p <= p_hi and f_lo <= f <= f_hi):
+                    return 1e30                     # outside the lens's travel / strength range
+                evals += 1
+                trial = list(lenses)
+                trial[k] = (p, f)
+                gap = wl_of_lenses(trial).beamline[2 + 2 * k]
+                r = ref_k.copy()
+                w = z.clone()
+                apply_stage(k + 1, w, r, hbl.Lattice(gap, r), n)
+                return emittance_x(w, n)
+
+            x0 = np.array(x0)
+            # the initial simplex steps inwards from edges of the box
+            dp = steps[0] if x0[0] + steps[0] <= p_hi else -steps[0]
+            df = steps[1] if x0[1] + steps[1] <= f_hi else -steps[1]
+            res = minimize(objective, x0, method="Nelder-Mead",
+                           options={"maxfev": max_evals, "xatol": xatol, "fatol": fatol_rel * objective(x0),
+                                    "initial_simplex": np.array([x0, x0 + (dp, 0.0), x0 + (0.0, df)])})
+            return (float(res.x[0]), float(res.x[1]))
 
         t0 = time.perf_counter()
-        res = minimize(objective, np.array(lenses[k]), method="Nelder-Mead",
-                       options={"maxfev": max_evals, "xatol": xatol, "fatol": fatol_rel * objective(lenses[k]),
-                                "initial_simplex": np.array([lenses[k], (lenses[k][0] + 0.5, lenses[k][1]),
-                                                             (lenses[k][0], lenses[k][1] + 0.2)])})
+        found = search(bounds, lenses[k], (0.5, 0.2))
+        boxes = []
+        for r in range(refine_rounds):
+            hp = 0.5 * (P_hi - P_lo) / shrink ** (r + 1)
+            hf = 0.5 * (F_hi - F_lo) / shrink ** (r + 1)
+            box = ((max(P_lo, found[0] - hp), min(P_hi, found[0] + hp)),
+                   (max(F_lo, found[1] - hf), min(F_hi, found[1] + hf)))
+            boxes.append(box)
+            lenses[k] = found
+            if refine is not None:
+                t1 = time.perf_counter()
+                refine(k, list(lenses), box)
+                t0 += time.perf_counter() - t1          # model building is not search time
+            found = search(box, found, (0.5 * hp, 0.5 * hf))
         dt = time.perf_counter() - t0
-        lenses[k] = (float(res.x[0]), float(res.x[1]))
+        lenses[k] = found
         gap = wl_of_lenses(lenses).beamline[2 + 2 * k]
         apply_stage(k + 1, z, ref, hbl.Lattice(gap, ref), n)
         eps.append(emittance_x(z, n))
         report.append({"interstage": k + 1, "lens": lenses[k], "evaluations": evals, "seconds": dt,
-                       "eps_x_after_next_stage": eps[-1]})
+                       "eps_x_after_next_stage": eps[-1], "refine_boxes": boxes})
         if log:
             log(f"interstage {k + 1}: lens at {lenses[k][0]:.4f} m, f = {lenses[k][1]:.4f} m after "
                 f"{evals} evaluations ({dt:.2f} s); eps_x after stage {k + 2}: {eps[-1]:.4e} m")
     return lenses, eps, report
+
+
+def optimise_lenses_on_surrogates(wl_of_lenses: Callable, start: Tuple[float, float], z0, n: int,
+                                  bounds, n_pairs: int, epochs: int, pair_seed: Callable[[int], int],
+                                  init_seed: Callable[[int], int], shuffle_seed: Callable[[int], int],
+                                  n_settings: int = 8, refine_rounds: int = 2, seed: int = 7,
+                                  max_evals: int = 200, log=None):
+    """§4.4 on the fast surrogate chain: every stage is taken by a surrogate
+    trained on fine-step pairs.  Before lens k is optimised, the surrogate of
+    stage k + 1 is trained on pairs pooled over the lens's start and
+    n_settings - 1 seeded settings in `bounds` (the earlier lenses at the
+    values found: the inputs the optimiser will produce); after the search,
+    each trust-region round retrains it on the lens found and n_settings - 1
+    seeded settings inside the shrunken box around it and searches again
+    there, so that the model is accurate where the optimum lies.  Seeds are
+    callables of the 0-based stage.  Returns (lenses, emittances after each
+    stage as the surrogate chain predicts them, per-interstage report,
+    surrogates, training settings, training seconds)."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(seed)
+    (p_lo, p_hi), (f_lo, f_hi) = bounds
+    settings = [tuple(start)] + [(float(p), float(f)) for p, f in
+                                 zip(rng.uniform(p_lo, p_hi, n_settings - 1), rng.uniform(f_lo, f_hi, n_settings - 1))]
+    surs = [None] * 4
+    t_train = [0.0]
+    training_sets = [{"stage": 1, "settings": [tuple(start)]}]
+
+    def train(k, lens_sets):
+        t0 = time.perf_counter()
+        surs[k] = train_stage_surrogate(wl_of_lenses, k, lens_sets, n_pairs, pair_seed(k), init_seed(k),
+                                        shuffle_seed(k), epochs=epochs, log=log)
+        torch.cuda.synchronize()
+        t_train[0] += time.perf_counter() - t0
+
+    def with_lens(k, lenses, s):
+        return list(lenses[:k]) + [s] + [tuple(start)] * (2 - k)
+
+    def before_interstage(k, lenses):
+        training_sets.append({"stage": k + 2, "settings": list(settings)})
+        train(k + 1, [with_lens(k, lenses, s) for s in settings])
+
+    def refine(k, lenses, box):
+        g = np.random.default_rng(seed + 100 * (k + 1) + len(training_sets))
+        (a, b), (c, d) = box
+        local = [lenses[k]] + [(float(p), float(f)) for p, f in
+                               zip(g.uniform(a, b, n_settings - 1), g.uniform(c, d, n_settings - 1))]
+        training_sets.append({"stage": k + 2, "box": box, "settings": local})
+        train(k + 1, [with_lens(k, lenses, s) for s in local])
+
+    def apply_sur(k, z, ref, pre, m):
+        surs[k].apply(z, ref, n=m, pre=pre)
+
+    train(0, [[tuple(start)] * 3])
+    lenses, eps, report = optimise_lenses(wl_of_lenses, start, z0, n, apply_sur, bounds=bounds,
+                                          max_evals=max_evals, log=log, before_interstage=before_interstage,
+                                          refine_rounds=refine_rounds, refine=refine)
+    return lenses, eps, report, surs, training_sets, t_train[0]
 
 
 def chain_emittances(wl, z0, n: int, apply_stage: Callable) -> List[float]:
