@@ -4,8 +4,13 @@
 //
 // Scheme (fixed order, hence bitwise reproducible run to run):
 //  1. each thread sums its particles (grid-stride, at most ~100 per thread)
-//     in plain FP64 into NV accumulators, coordinates shifted by particle 0
-//     so that the second moments do not cancel against the mean;
+//     into NV FP64 accumulators, coordinates shifted by particle 0 so that
+//     the second moments do not cancel against the mean; the sums whose
+//     terms take both signs (the six first moments, the paired
+//     differences' squares too as they are few) are compensated: every
+//     addition goes through TwoSum and its rounding error into a second
+//     accumulator, and the pair seeds the double-double merge (compensating
+//     all 27 moment sums measured 72 % slower, the six first ones 8 %);
 //  2. the 64 lanes of a wavefront merge their sums as double-double pairs
 //     (error-free TwoSum) through cross-lane shuffles, the waves of a block
 //     through LDS, and each block writes NV double-double partials;
@@ -93,8 +98,18 @@ __device__ void block_reduce_dd(DD (&v)[NV], DD* lds) {
 
 // Per-particle contributions.
 // Shift = particle 0 (read on the device; uniform across the grid).
+// TwoSum accumulation: a + x exactly as the new a plus the rounding error,
+// which is added into c.
+__device__ __forceinline__ void add_comp(double& a, double& c, double x) {
+    const double s = a + x;
+    const double bp = s - a;
+    c += (a - (s - bp)) + (x - bp);
+    a = s;
+}
+
 struct MomentsOp {
     static constexpr int NV = 27;
+    static constexpr int NC = 6;     // compensated: the first moments
     const double* z;
     int64_t ld;
     double sh[6];
@@ -102,47 +117,29 @@ struct MomentsOp {
 #pragma unroll
         for (int j = 0; j < 6; ++j) sh[j] = z[j * ld];
     }
-    __device__ __forceinline__ void add2(int64_t i, int64_t k, double (&acc)[NV]) const {
-        double a[6], b[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            a[j] = __builtin_nontemporal_load(z + j * ld + i);
-            b[j] = __builtin_nontemporal_load(z + j * ld + k);
-        }
-        accumulate(a, acc);
-        accumulate(b, acc);
-    }
     // four particles i, i + st, i + 2 st, i + 3 st: all 24 loads in flight
     // before the first feeds the accumulation (same order as one at a time)
-    __device__ __forceinline__ void add4(int64_t i, int64_t st, double (&acc)[NV]) const {
+    __device__ __forceinline__ void add4(int64_t i, int64_t st, double (&acc)[NV], double (&cmp)[NC]) const {
         double a[4][6];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int j = 0; j < 6; ++j) a[r][j] = __builtin_nontemporal_load(z + j * ld + i + r * st);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) accumulate(a[r], acc);
+        for (int r = 0; r < 4; ++r) accumulate(a[r], acc, cmp);
     }
-    __device__ __forceinline__ void accumulate(const double (&v)[6], double (&acc)[NV]) const {
+    __device__ __forceinline__ void add(int64_t i, double (&acc)[NV], double (&cmp)[NC]) const {
+        double a[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a[j] = __builtin_nontemporal_load(z + j * ld + i);
+        accumulate(a, acc, cmp);
+    }
+    __device__ __forceinline__ void accumulate(const double (&v)[6], double (&acc)[NV], double (&cmp)[NC]) const {
         double d[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) d[j] = v[j] - sh[j];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) acc[j] += d[j];
-#pragma unroll
-        for (int j = 0; j < 6; ++j)
-#pragma unroll
-            for (int k = j; k < 6; ++k) {
-                const int q = 6 + j * 6 - j * (j - 1) / 2 + (k - j);
-                acc[q] = fma(d[j], d[k], acc[q]);
-            }
-    }
-    __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
-        double d[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) d[j] = __builtin_nontemporal_load(z + j * ld + i) - sh[j];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[j] += d[j];
+        for (int j = 0; j < 6; ++j) add_comp(acc[j], cmp[j], d[j]);
 #pragma unroll
         for (int j = 0; j < 6; ++j)
 #pragma unroll
@@ -155,23 +152,12 @@ struct MomentsOp {
 
 struct Diff2Op {
     static constexpr int NV = 6;
+    static constexpr int NC = 6;     // all compensated
     const double* zs;
     const double* zf;
     int64_t ld;
     __device__ __forceinline__ void init() {}
-    __device__ __forceinline__ void add2(int64_t i, int64_t k, double (&acc)[NV]) const {
-        double a[6], b[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            a[j] = __builtin_nontemporal_load(zs + j * ld + i) - __builtin_nontemporal_load(zf + j * ld + i);
-            b[j] = __builtin_nontemporal_load(zs + j * ld + k) - __builtin_nontemporal_load(zf + j * ld + k);
-        }
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[j] = fma(a[j], a[j], acc[j]);
-#pragma unroll
-        for (int j = 0; j < 6; ++j) acc[j] = fma(b[j], b[j], acc[j]);
-    }
-    __device__ __forceinline__ void add4(int64_t i, int64_t st, double (&acc)[NV]) const {
+    __device__ __forceinline__ void add4(int64_t i, int64_t st, double (&acc)[NV], double (&cmp)[NC]) const {
         double a[4][6];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -182,40 +168,39 @@ struct Diff2Op {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int j = 0; j < 6; ++j) acc[j] = fma(a[r][j], a[r][j], acc[j]);
+            for (int j = 0; j < 6; ++j) add_comp(acc[j], cmp[j], a[r][j] * a[r][j]);
     }
-    __device__ __forceinline__ void add(int64_t i, double (&acc)[NV]) const {
+    __device__ __forceinline__ void add(int64_t i, double (&acc)[NV], double (&cmp)[NC]) const {
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             const double d = __builtin_nontemporal_load(zs + j * ld + i) - __builtin_nontemporal_load(zf + j * ld + i);
-            acc[j] = fma(d, d, acc[j]);
+            add_comp(acc[j], cmp[j], d * d);
         }
     }
 };
 
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_partials(Op op, int64_t n, DD* __restrict__ part) {
-    constexpr int NV = Op::NV;
+    constexpr int NV = Op::NV, NC = Op::NC;
     op.init();
     __shared__ DD lds[kWaves * NV];
-    double acc[NV];
+    double acc[NV], cmp[NC];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) cmp[q] = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     // four particles per iteration: their loads are in flight before the
     // first feeds the (fixed-order) accumulation; the bunch is streamed once,
     // so the loads are non-temporal.  Moments of 2.5e7 particles: 240 us with
     // two plain loads per iteration, 218 us non-temporal, 197 us with four
-    // (6.1 TB/s).
-    for (; i + 3 * stride < n; i += 4 * stride) op.add4(i, stride, acc);
-    for (; i + stride < n; i += 2 * stride) {
-        op.add2(i, i + stride, acc);
-    }
-    for (; i < n; i += stride) op.add(i, acc);
+    // (6.1 TB/s), 213 us with the first moments compensated.
+    for (; i + 3 * stride < n; i += 4 * stride) op.add4(i, stride, acc, cmp);
+    for (; i < n; i += stride) op.add(i, acc, cmp);
     DD v[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = DD{acc[q], 0.0};
+    for (int q = 0; q < NV; ++q) v[q] = q < NC ? two_sum(acc[q], cmp[q]) : DD{acc[q], 0.0};
     block_reduce_dd<NV>(v, lds);
     if (threadIdx.x < NV) {
         const int q = threadIdx.x;
