@@ -252,7 +252,15 @@ typedef struct hbl_mlp_shape {
  * test outputs have the emittances of (x, px) and (y, py) (§4) closest to
  * those of the true test outputs (the lowest max over the two planes of
  * |eps_pred / eps_true - 1|; keeps a 36.6 KB parameter snapshot per epoch of
- * that quarter in device memory during the call).  reserved must be 0. */
+ * that quarter in device memory during the call).  resume (0 or 1): with 1
+ * the call continues an earlier training of this handle (or of the model it
+ * was loaded from): the normalisation, the Adam moments and the step count
+ * are kept, not reset; the step count must be a whole number E of epochs of
+ * this call's recipe, and the epochs are numbered from E on (their
+ * Fisher-Yates orders are those of epochs E, E + 1, ...); the learning-rate
+ * schedule spans this call's steps.  With the same pairs, recipe and a
+ * constant rate, training E epochs, saving, loading and resuming for F more
+ * gives the parameters of one run of E + F epochs, bit for bit. */
 typedef struct hbl_train_cfg {
     int32_t batch;
     int32_t epochs;
@@ -261,7 +269,7 @@ typedef struct hbl_train_cfg {
     double train_frac;
     uint64_t shuffle_seed;
     int32_t keep_best;
-    int32_t reserved;
+    int32_t resume;
 } hbl_train_cfg;
 
 /* Create a surrogate with parameters U(-1/sqrt(fan_in), 1/sqrt(fan_in)):
@@ -389,8 +397,8 @@ hbl_status hbl_prelu_loss_grad(hbl_prelu_net* m, const double* zin, const double
 /* Train as hbl_surrogate_train (normalisation from the training split, Adam
  * reset, half-cosine learning rate, Fisher-Yates epoch order, test loss per
  * epoch), entirely on the device; batch any size in [1, 16384] (§4.2 uses
- * 1200).  cfg->keep_best must be 0 here (HBL_EINVAL otherwise).  SYNC at the
- * end; loss_log as for hbl_surrogate_train. */
+ * 1200).  cfg->keep_best and cfg->resume must be 0 here (HBL_EINVAL
+ * otherwise).  SYNC at the end; loss_log as for hbl_surrogate_train. */
 hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zout, int64_t n_pairs,
                            int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream);
 

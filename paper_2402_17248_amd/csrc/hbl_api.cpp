@@ -1144,33 +1144,40 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
     HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "surrogate_train: train_frac must be in (0, 1]");
     HBL_REQUIRE(n_pairs <= INT32_MAX, "surrogate_train: at most 2^31-1 pairs");
     HBL_REQUIRE(cfg->keep_best >= 0 && cfg->keep_best <= 2, "surrogate_train: keep_best must be 0, 1 or 2");
-    HBL_REQUIRE(cfg->reserved == 0, "surrogate_train: reserved must be 0");
+    HBL_REQUIRE(cfg->resume == 0 || cfg->resume == 1, "surrogate_train: resume must be 0 or 1");
+    HBL_REQUIRE(!cfg->resume || m->has_norm, "surrogate_train: resume needs a trained or loaded model");
     const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
     const int64_t n_test = n_pairs - n_train;
     HBL_REQUIRE(n_train >= cfg->batch, "surrogate_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);
+    const int32_t nb = cfg->batch / 64;
+    const int64_t steps_per_epoch = n_train / cfg->batch;
+    HBL_REQUIRE(!cfg->resume || m->step % steps_per_epoch == 0,
+                "surrogate_train: resume needs the step count (%lld) to be a whole number of epochs of %lld steps",
+                (long long)m->step, (long long)steps_per_epoch);
+    const int64_t epoch0 = cfg->resume ? m->step / steps_per_epoch : 0;
     if (hbl_status st = check_device(zin, bunch_bytes(n_pairs, ld), "surrogate_train(in)")) return st;
     if (hbl_status st = check_device(zout, bunch_bytes(n_pairs, ld), "surrogate_train(out)")) return st;
     hipStream_t s = (hipStream_t)stream;
-    // normalisation from the training split (§3), FP64 compensated moments
-    double mi[6], ci[21], mo[6], co[21];
-    if (hbl_status st = hbl_moments(zin, n_train, ld, mi, ci, stream)) return st;
-    if (hbl_status st = hbl_moments(zout, n_train, ld, mo, co, stream)) return st;
-    double norm[24];
-    for (int j = 0; j < 6; ++j) {
-        const int d = j * 6 - j * (j - 1) / 2;
-        norm[j] = mi[j];
-        norm[6 + j] = sqrt(ci[d]);
-        norm[12 + j] = mo[j];
-        norm[18 + j] = sqrt(co[d]);
+    if (!cfg->resume) {
+        // normalisation from the training split (§3), FP64 compensated moments
+        double mi[6], ci[21], mo[6], co[21];
+        if (hbl_status st = hbl_moments(zin, n_train, ld, mi, ci, stream)) return st;
+        if (hbl_status st = hbl_moments(zout, n_train, ld, mo, co, stream)) return st;
+        double norm[24];
+        for (int j = 0; j < 6; ++j) {
+            const int d = j * 6 - j * (j - 1) / 2;
+            norm[j] = mi[j];
+            norm[6 + j] = sqrt(ci[d]);
+            norm[12 + j] = mo[j];
+            norm[18 + j] = sqrt(co[d]);
+        }
+        if (hbl_status st = check_norm(norm)) {
+            set_error(HBL_EINVAL, "surrogate_train: a coordinate has zero spread in the training split");
+            return st;
+        }
+        memcpy(m->norm, norm, sizeof norm);
+        m->has_norm = true;
     }
-    if (hbl_status st = check_norm(norm)) {
-        set_error(HBL_EINVAL, "surrogate_train: a coordinate has zero spread in the training split");
-        return st;
-    }
-    memcpy(m->norm, norm, sizeof norm);
-    m->has_norm = true;
-    const int32_t nb = cfg->batch / 64;
-    const int64_t steps_per_epoch = n_train / cfg->batch;
     if (hbl_status st = ensure_train_scratch(m, nb, 2 * (cfg->epochs > 0 ? cfg->epochs : 1))) return st;
     const bool keep_best = cfg->keep_best && n_test > 0 && cfg->epochs > 0;
     const bool by_eps = keep_best && cfg->keep_best == 2;
@@ -1182,12 +1189,15 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
         }
     }
     if (keep_best) HBL_HIP(launch_best_init(m->d_best_info, s));
-    // fresh Adam state
-    HBL_HIP(hipMemsetAsync(m->d_m, 0, sizeof(float) * kMlpParams, s));
-    HBL_HIP(hipMemsetAsync(m->d_v, 0, sizeof(float) * kMlpParams, s));
+    // fresh Adam state (kept when resuming)
+    if (!cfg->resume) {
+        HBL_HIP(hipMemsetAsync(m->d_m, 0, sizeof(float) * kMlpParams, s));
+        HBL_HIP(hipMemsetAsync(m->d_v, 0, sizeof(float) * kMlpParams, s));
+        m->step = 0;
+    }
     HBL_HIP(hipMemsetAsync(m->d_loss_acc, 0, sizeof(double) * 2 * (cfg->epochs > 0 ? cfg->epochs : 1), s));
     if (hbl_status st = repack(m, s)) return st;
-    m->step = 0;
+    const int64_t step0 = m->step;
     // double-buffered epoch orders: host pinned -> device
     int32_t* h_perm[2] = {nullptr, nullptr};
     int32_t* d_perm[2] = {nullptr, nullptr};
@@ -1231,7 +1241,7 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
     std::vector<int64_t> steps_done(cfg->epochs > 0 ? cfg->epochs : 1, 0);
     int64_t planned = (int64_t)cfg->epochs * steps_per_epoch;
     if (cfg->max_steps >= 0 && cfg->max_steps < planned) planned = cfg->max_steps;
-    auto lr_at = [&](int64_t t) {  // t = 1..planned, half-cosine anneal
+    auto lr_at = [&](int64_t t) {  // t = 1..planned (this call's steps), half-cosine anneal
         if (planned <= 1 || cfg->lr_final == cfg->lr) return (double)cfg->lr;
         const double ph = 3.14159265358979323846 * (double)(t - 1) / (double)(planned - 1);
         return (double)cfg->lr_final + 0.5 * ((double)cfg->lr - (double)cfg->lr_final) * (1.0 + cos(ph));
@@ -1240,19 +1250,19 @@ hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double
         const int k = (int)(ep & 1);
         hipError_t e = hipEventSynchronize(ev[k]);   // the copy two epochs ago has finished
         if (e != hipSuccess) { fail(HBL_EHIP, "event wait", e); break; }
-        epoch_order(h_perm[k], n_train, cfg->shuffle_seed, ep);
+        epoch_order(h_perm[k], n_train, cfg->shuffle_seed, epoch0 + ep);
         e = hipMemcpyAsync(d_perm[k], h_perm[k], sizeof(int32_t) * n_train, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipEventRecord(ev[k], s);
         if (e != hipSuccess) { fail(HBL_EHIP, "order upload", e); break; }
         for (int64_t step = 0; step < steps_per_epoch; ++step) {
-            if (cfg->max_steps >= 0 && m->step >= cfg->max_steps) break;
+            if (cfg->max_steps >= 0 && m->step - step0 >= cfg->max_steps) break;
             m->step += 1;
             e = launch_train_step(zin, zout, ld, d_perm[k] + step * cfg->batch, cfg->batch, m->d_img,
                                   m->d_part, m->d_loss_part, m->norm, s);
             if (e == hipSuccess)
                 e = launch_train_adam(m->d_params, m->d_m, m->d_v, m->d_part, nb, m->d_loss_part,
                                       m->d_loss_acc + 2 * ep, 1.0 / ((double)cfg->batch * 6.0), m->step,
-                                      (float)lr_at(m->step), cfg->beta1, cfg->beta2, cfg->eps, s);
+                                      (float)lr_at(m->step - step0), cfg->beta1, cfg->beta2, cfg->eps, s);
             if (e == hipSuccess) e = launch_mlp_pack(m->d_params, m->d_img, s);
             if (e != hipSuccess) { fail(HBL_EHIP, "step launch", e); break; }
             steps_done[ep] += 1;
@@ -1845,8 +1855,8 @@ hbl_status hbl_prelu_train(hbl_prelu_net* m, const double* zin, const double* zo
     HBL_REQUIRE(isfinite(cfg->eps) && cfg->eps > 0, "prelu_train: eps must be > 0");
     HBL_REQUIRE(cfg->train_frac > 0.0 && cfg->train_frac <= 1.0, "prelu_train: train_frac must be in (0, 1]");
     HBL_REQUIRE(n_pairs <= INT32_MAX, "prelu_train: at most 2^31-1 pairs");
-    HBL_REQUIRE(cfg->keep_best == 0 && cfg->reserved == 0,
-                "prelu_train: keep_best is not supported by the paper-shaped network (must be 0)");
+    HBL_REQUIRE(cfg->keep_best == 0 && cfg->resume == 0,
+                "prelu_train: keep_best and resume are not supported by the paper-shaped network (must be 0)");
     const int64_t n_train = llround(cfg->train_frac * (double)n_pairs);
     const int64_t n_test = n_pairs - n_train;
     HBL_REQUIRE(n_train >= cfg->batch, "prelu_train: %lld training pairs < batch %d", (long long)n_train, cfg->batch);

@@ -55,7 +55,7 @@ class TrainCfg(C.Structure):
     _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("max_steps", C.c_int64), ("lr", C.c_float),
                 ("lr_final", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("train_frac", C.c_double), ("shuffle_seed", C.c_uint64), ("keep_best", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("resume", C.c_int32)]
 
 
 def _load():
@@ -353,17 +353,20 @@ class Surrogate:
         _call("hbl_surrogate_set_stage", self._h, C.byref(el), C.byref(ref_at_entry))
 
     def train(self, zin, zout, n_pairs, batch=4096, epochs=1, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-              train_frac=0.7, shuffle_seed=0, max_steps=-1, lr_final=None, keep_best=False, stream=None):
+              train_frac=0.7, shuffle_seed=0, max_steps=-1, lr_final=None, keep_best=False, resume=False,
+              stream=None):
         """keep_best: 0/False the last epoch's parameters; 1/True those of the
         lowest test loss; 2 those (among the last quarter of the epochs) whose
-        test-split emittances in x and y are closest to the true ones."""
+        test-split emittances in x and y are closest to the true ones.
+        resume: continue an earlier training (normalisation, Adam state and
+        epoch numbering kept)."""
         import numpy as np
         pin, _, ld = _bunch_args(zin, n_pairs, "input pairs")
         pout, _, ldo = _bunch_args(zout, n_pairs, "output pairs")
         if ldo != ld:
             raise ValueError("train: input and output pairs need the same leading dimension")
         cfg = TrainCfg(batch, epochs, max_steps, lr, lr if lr_final is None else lr_final, beta1, beta2, eps,
-                       train_frac, shuffle_seed, int(keep_best), 0)
+                       train_frac, shuffle_seed, int(keep_best), int(bool(resume)))
         log = np.zeros(2 * max(epochs, 1), dtype=np.float32)
         _call("hbl_surrogate_train", self._h, pin, pout, n_pairs, ld, C.byref(cfg),
               log.ctypes.data_as(C.POINTER(C.c_float)), stream or current_stream())

@@ -164,8 +164,9 @@ def test_surrogate_chain_parity(hbl, orc, n, n_stages):
     c1, _ = oracle_surrogate_chain(orc, wl, nets, c.copy(), mode=1)
     d1 = np.abs(g - c1) / sd
     print(f"vs kernel emulation: median {np.median(d1):.2e} max {d1.max():.2e}", flush=True)
-    assert np.median(d1) < 1e-5, np.median(d1)
-    assert d1.max() < 0.05 * n_stages, d1.max()
+    # measured: median ~1e-9, max 1.4e-2 / 1.6e-2 (4 / 2 stages: a rare RNE flip of a bf16 activation)
+    assert np.median(d1) < 1e-8, np.median(d1)
+    assert d1.max() < 0.05, d1.max()
 
 
 def test_pairs_record_stage_input(hbl, orc):

@@ -78,7 +78,7 @@ def test_loss_grad_matches_oracle(hbl, orc, pairs, width, hidden, batch):
     loss_g, g = net.loss_grad(rec, out, idx)
     loss_o, go = orc.prelu_loss_grad(sh, p, norm, xin, xout, idx.astype(np.int64))
     print(f"{width}x{hidden}: loss {loss_g:.6g} vs {loss_o:.6g}; total rel {rel_fro(g.astype(float), go):.3e}")
-    assert abs(loss_g / loss_o - 1) < 1e-2
+    assert abs(loss_g / loss_o - 1) < 1e-3          # the derivation above; measured <= 6.5e-5
     assert rel_fro(g.astype(np.float64), go) < 3e-2
     for name, a, b in blocks(sh):
         r = rel_fro(g[a:b].astype(np.float64), go[a:b])
@@ -105,7 +105,12 @@ def test_gradient_ignores_samples_past_the_batch(hbl, orc, pairs):
 def test_training_matches_oracle_loop(hbl, orc, pairs):
     """Three epochs of the library's training against the oracle's loss
     gradient and Adam driven through the same epoch orders and learning-rate
-    schedule: the parameters move the same way and the losses agree."""
+    schedule: the parameters move the same way and the losses agree.  Each
+    step's gradient differs from the exact one by ~1e-2 relative (the bf16
+    products, module docstring); Adam's normalised steps turn that into
+    parameter differences of a few 1e-3 of the motion (measured 0.6 %, bound
+    3 %), and the per-epoch losses into differences of ~1e-3 (measured
+    1.4e-3 at most, bound 1e-2)."""
     n, rec, out, xin, xout = pairs
     W_, H_, B, E, lr, lr_final = 64, 2, 256, 3, 3e-3, 3e-4
     sh = orc.shape(width=W_, hidden=H_)
@@ -141,8 +146,8 @@ def test_training_matches_oracle_loop(hbl, orc, pairs):
           np.linalg.norm(pg - p) / moved)
     assert np.all(np.isfinite(log))
     assert log[-1, 1] < 0.7 * log[0, 1]
-    assert np.all(np.abs(log / olog - 1) < 0.1), (log, olog)
-    assert np.linalg.norm(pg - p) < 0.25 * moved
+    assert np.all(np.abs(log / olog - 1) < 1e-2), (log, olog)
+    assert np.linalg.norm(pg - p) < 0.03 * moved
 
 
 def test_save_load_roundtrip(hbl, orc, pairs, tmp_path):

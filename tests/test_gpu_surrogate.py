@@ -353,3 +353,35 @@ def test_keep_best_by_test_split_emittance(hbl, orc, pairs):
     srt = sorted(cand)
     assert len(srt) < 2 or not np.isfinite(srt[1]) or srt[1] - srt[0] > 1e-12 * srt[1]   # a clear winner
     assert np.array_equal(a.get_params(), params[k])
+
+
+def test_resume_after_save_and_load(hbl, orc, pairs):
+    """Checkpoint and resume: 2 epochs, save, load into a new handle, resume
+    for 3 more equals one run of 5 epochs bit for bit (constant rate: the
+    schedule then does not depend on the call; same pairs and recipe), the
+    resumed call's losses equal the single run's epochs 2-4, and a resume
+    that cannot continue (no model, or a step count that is not a whole
+    number of epochs) is rejected before anything runs."""
+    n, rec, out, _, _, stage, entry = pairs
+    cfg = dict(batch=256, lr=2e-3, shuffle_seed=3)
+    a = hbl.Surrogate(41)
+    log_a = a.train(rec, out, n, epochs=2, **cfg)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ckpt.hbls")
+        a.save(path)
+        b = hbl.Surrogate.load(path)
+    log_b = b.train(rec, out, n, epochs=3, resume=True, **cfg)
+    c = hbl.Surrogate(41)
+    log_c = c.train(rec, out, n, epochs=5, **cfg)
+    print(f"resume: single-run test losses {log_c[:, 1].tolist()}, 2 + 3 resumed {log_a[:, 1].tolist()} "
+          f"{log_b[:, 1].tolist()}", flush=True)
+    assert np.array_equal(log_a, log_c[:2]) and np.array_equal(log_b, log_c[2:])
+    assert np.array_equal(b.get_params(), c.get_params())
+    with pytest.raises(hbl.HblError) as ei:
+        hbl.Surrogate(42).train(rec, out, n, epochs=1, resume=True, **cfg)
+    assert ei.value.status == hbl.HBL_EINVAL
+    e = hbl.Surrogate(43)
+    e.train(rec, out, n, epochs=1, max_steps=5, **cfg)
+    with pytest.raises(hbl.HblError) as ei:
+        e.train(rec, out, n, epochs=1, resume=True, **cfg)
+    assert ei.value.status == hbl.HBL_EINVAL and "whole number of epochs" in str(ei.value)
