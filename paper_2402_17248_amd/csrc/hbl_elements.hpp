@@ -127,6 +127,17 @@ __device__ __forceinline__ void store6_nt(double* __restrict__ z, int64_t ld, in
     __builtin_nontemporal_store(p.pt, z + 5 * ld + i);
 }
 
+// The five rows a lattice element can change: no drift, quadrupole, bend or
+// thin lens (chromatic or not) changes pt, so a lattice pass stores 40 of
+// the 48 bytes of a particle.
+__device__ __forceinline__ void store5_nt(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
+    __builtin_nontemporal_store(p.x, z + i);
+    __builtin_nontemporal_store(p.y, z + ld + i);
+    __builtin_nontemporal_store(p.t, z + 2 * ld + i);
+    __builtin_nontemporal_store(p.px, z + 3 * ld + i);
+    __builtin_nontemporal_store(p.py, z + 4 * ld + i);
+}
+
 __device__ __forceinline__ void store6(double* __restrict__ z, int64_t ld, int64_t i, const P6& p) {
     z[i] = p.x;
     z[ld + i] = p.y;

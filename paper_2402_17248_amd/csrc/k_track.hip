@@ -154,7 +154,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_gaussian(double* __restrict__ z
 // wavefront-uniform scalar loads, the drift test a scalar branch).  One tile
 // of kPer*kBlock particles per block (grid-stride beyond 2^20 blocks): a
 // persistent, capped grid measured 20 % slower, and a switch over all the
-// element kinds cost more in register copies than the FMAs it saves.
+// element kinds cost more in register copies than the FMAs it saves.  Reads
+// the six rows and writes back the five an element can change (88 B per
+// particle): no lattice element changes pt.
 template <bool CHROM, int kPer>
 __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z, int64_t n,
                                                           int64_t ld, const double* __restrict__ gen,
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = base + k * kBlock + threadIdx.x;
-            if (live[k]) store6_nt(z, ld, i, p[k]);
+            if (live[k]) store5_nt(z, ld, i, p[k]);         // pt is never changed by a lattice element
         }
     }
 }
