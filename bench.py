@@ -197,8 +197,9 @@ def cpu_leg(make, run, budget_s, n_max, threads, per_particle=None, min_s=0.25):
     m1 = int(max(64, min(n_max, 0.5 * budget_s / max(t_small, 1e-12))))
     z1 = make(m1, 0)
     t1 = timed([z1.copy()])
-    r1 = max(1, math.ceil(min_s / max(t1, 1e-9))) if t1 < min_s else 1
-    if r1 > 1:
+    r1 = 1
+    while t1 < min_s and r1 < 1024:        # warm repeats can run faster than the first: re-check
+        r1 = min(1024, max(2 * r1, math.ceil(1.25 * min_s * r1 / max(t1, 1e-9))))
         t1 = timed([z1.copy() for _ in range(r1)])
     m2 = min(n_max, m1 * threads)
     per = (m2 + threads - 1) // threads
