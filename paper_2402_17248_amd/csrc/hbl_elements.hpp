@@ -98,6 +98,107 @@ __device__ __forceinline__ void apply_elements(P6& p, const LatticeView& lv) {
     for (int32_t e = 0; e < lv.n; ++e) el_unified<CHROM>(p, lv.gen + (int64_t)e * kGen);
 }
 
+// ---------------------------------------------------------------- asm element loop
+// The element loop of an achromatic lattice as the text of one inline-asm
+// block, shared by the kernels that apply lattices.  Written in C, a branch
+// on the element kind is restructured by the compiler into flow blocks whose
+// joins move the particle state between register sets (a 64-bit copy per
+// coordinate and element); in the asm block the state is tied in place
+// ("+v" operands x<k>, y<k>, t<k>, px<k>, py<k>; inputs pt<k>), each map
+// updates it in place with one temporary w<k> per particle (a plane at a
+// time), and the only copies left are the two a 2x2 plane map needs.  The
+// operations and their order are those of el_drift_gen, el_quad_gen and
+// el_unified<false>, so results are bitwise those of the C maps.
+//
+// Per element the kind (s90) and the 13 achromatic coefficients of its
+// record (s[64:89]) are read with scalar loads and waited for inside the
+// block (no load is left in flight at its end); there are no scalar stores.
+// Operands: [gp] record table, [kp] kinds (SGPR pointers), [off] / [koff]
+// byte offsets (start at 0), [cnt] element count (>= 1; the block runs a
+// do-while loop).  OP applies "op dst, coef, src" to every particle of the
+// block, MOV copies a coordinate.
+static_assert(kGen == 24 && kDrift == 1 && kQuad == 2, "the asm loop hard-codes the record stride and kinds");
+
+#define HBL_G0 "s[64:65]"
+#define HBL_G1 "s[66:67]"
+#define HBL_G2 "s[68:69]"
+#define HBL_G3 "s[70:71]"
+#define HBL_G4 "s[72:73]"
+#define HBL_G5 "s[74:75]"
+#define HBL_G6 "s[76:77]"
+#define HBL_G7 "s[78:79]"
+#define HBL_G8 "s[80:81]"
+#define HBL_G9 "s[82:83]"
+#define HBL_G10 "s[84:85]"
+#define HBL_G11 "s[86:87]"
+#define HBL_G12 "s[88:89]"
+
+#define HBL_OP1(op, d, c, s) op " %[" d "0], " c ", %[" s "0]\n\t"
+#define HBL_MOV1(d, s) "v_mov_b64 %[" d "0], %[" s "0]\n\t"
+#define HBL_OP4(op, d, c, s)                                                         \
+    op " %[" d "0], " c ", %[" s "0]\n\t" op " %[" d "1], " c ", %[" s "1]\n\t"      \
+    op " %[" d "2], " c ", %[" s "2]\n\t" op " %[" d "3], " c ", %[" s "3]\n\t"
+#define HBL_MOV4(d, s)                                                               \
+    "v_mov_b64 %[" d "0], %[" s "0]\n\tv_mov_b64 %[" d "1], %[" s "1]\n\t"           \
+    "v_mov_b64 %[" d "2], %[" s "2]\n\tv_mov_b64 %[" d "3], %[" s "3]\n\t"
+
+#define HBL_ELEMENT_LOOP(OP, MOV)                                                                      \
+    "L_elem_%=:\n\t"                                                                                   \
+    "s_load_dword s90, %[kp], %[koff]\n\t"                                                             \
+    "s_load_dwordx16 s[64:79], %[gp], %[off]\n\t"                                                      \
+    "s_add_u32 s91, %[off], 0x40\n\t"                                                                  \
+    "s_load_dwordx8 s[80:87], %[gp], s91\n\t"                                                          \
+    "s_add_u32 s91, %[off], 0x60\n\t"                                                                  \
+    "s_load_dwordx2 s[88:89], %[gp], s91\n\t"                                                          \
+    "s_add_u32 %[off], %[off], 0xc0\n\t"                                                               \
+    "s_add_u32 %[koff], %[koff], 4\n\t"                                                                \
+    "s_waitcnt lgkmcnt(0)\n\t"                                                                         \
+    "s_cmp_eq_u32 s90, 1\n\t"                                                                          \
+    "s_cbranch_scc1 L_drift_%=\n\t"                                                                    \
+    "s_cmp_eq_u32 s90, 2\n\t"                                                                          \
+    "s_cbranch_scc1 L_quad_%=\n\t"                                                                     \
+    /* unified record: t first (it reads the old x, px), then the x and y planes */                    \
+    OP("v_fmac_f64", "t", HBL_G10, "x") OP("v_fmac_f64", "t", HBL_G11, "px")                           \
+    OP("v_fmac_f64", "t", HBL_G12, "pt")                                                               \
+    OP("v_mul_f64", "w", HBL_G3, "x") OP("v_mul_f64", "x", HBL_G0, "x")                                \
+    OP("v_fmac_f64", "w", HBL_G4, "px") OP("v_fmac_f64", "x", HBL_G1, "px")                            \
+    OP("v_fmac_f64", "w", HBL_G5, "pt") OP("v_fmac_f64", "x", HBL_G2, "pt") MOV("px", "w")             \
+    OP("v_mul_f64", "w", HBL_G8, "y") OP("v_mul_f64", "y", HBL_G6, "y")                                \
+    OP("v_fmac_f64", "w", HBL_G9, "py") OP("v_fmac_f64", "y", HBL_G7, "py") MOV("py", "w")             \
+    "s_branch L_next_%=\n\t"                                                                           \
+    "L_drift_%=:\n\t"                                                                                  \
+    OP("v_fmac_f64", "x", HBL_G1, "px") OP("v_fmac_f64", "y", HBL_G7, "py")                            \
+    OP("v_fmac_f64", "t", HBL_G12, "pt")                                                               \
+    "s_branch L_next_%=\n\t"                                                                           \
+    "L_quad_%=:\n\t"                                                                                   \
+    OP("v_mul_f64", "w", HBL_G3, "x") OP("v_mul_f64", "x", HBL_G0, "x")                                \
+    OP("v_fmac_f64", "w", HBL_G4, "px") OP("v_fmac_f64", "x", HBL_G1, "px") MOV("px", "w")             \
+    OP("v_mul_f64", "w", HBL_G8, "y") OP("v_mul_f64", "y", HBL_G6, "y")                                \
+    OP("v_fmac_f64", "w", HBL_G9, "py") OP("v_fmac_f64", "y", HBL_G7, "py") MOV("py", "w")             \
+    OP("v_fmac_f64", "t", HBL_G12, "pt")                                                               \
+    "L_next_%=:\n\t"                                                                                   \
+    "s_sub_u32 %[cnt], %[cnt], 1\n\t"                                                                  \
+    "s_cmp_lg_u32 %[cnt], 0\n\t"                                                                       \
+    "s_cbranch_scc1 L_elem_%="
+
+#define HBL_ELEMENT_LOOP_CLOBBERS                                                                      \
+    "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77",  \
+        "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90",     \
+        "s91", "scc", "memory"
+
+// One particle through an achromatic lattice with the asm element loop.
+__device__ __forceinline__ void apply_elements_asm(P6& p, const LatticeView& lv) {
+    if (lv.n <= 0) return;
+    double w;
+    uint32_t off = 0, koff = 0;
+    int32_t cnt = lv.n;
+    asm volatile(HBL_ELEMENT_LOOP(HBL_OP1, HBL_MOV1)
+                 : [x0] "+v"(p.x), [y0] "+v"(p.y), [t0] "+v"(p.t), [px0] "+v"(p.px), [py0] "+v"(p.py),
+                   [w0] "=&v"(w), [off] "+s"(off), [koff] "+s"(koff), [cnt] "+s"(cnt)
+                 : [pt0] "v"(p.pt), [gp] "s"(lv.gen), [kp] "s"(lv.kinds)
+                 : HBL_ELEMENT_LOOP_CLOBBERS);
+}
+
 __device__ __forceinline__ void load6(const double* __restrict__ z, int64_t ld, int64_t i, P6& p) {
     p.x = z[i];
     p.y = z[ld + i];

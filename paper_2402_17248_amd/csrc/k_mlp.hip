@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
         P6 p;
         if (live) load6(z, ld, i, p);
         else p = P6{na.mu_in[0], na.mu_in[1], na.mu_in[2], na.mu_in[3], na.mu_in[4], na.mu_in[5]};
-        if (GAPS) apply_elements<CHROM>(p, pre);
+        if constexpr (GAPS && CHROM) apply_elements<true>(p, pre);
+        else if constexpr (GAPS) apply_elements_asm(p, pre);
         const double pv[6] = {p.x, p.y, p.t, p.px, p.py, p.pt};
         uint32_t hw[3], lw[3];
 #pragma unroll
@@ -309,7 +310,8 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
         q.px = fma(na.sd_out[3], (double)o[3], na.mu_out[3]);
         q.py = fma(na.sd_out[4], (double)o[4], na.mu_out[4]);
         q.pt = fma(na.sd_out[5], (double)o[5], na.mu_out[5]);
-        if (GAPS) apply_elements<CHROM>(q, post);
+        if constexpr (GAPS && CHROM) apply_elements<true>(q, post);
+        else if constexpr (GAPS) apply_elements_asm(q, post);
         if (live) store6(z, ld, i, q);
     }
 }

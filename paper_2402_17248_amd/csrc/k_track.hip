@@ -197,46 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused(double* __restrict__ z
     }
 }
 
-// Achromatic fused lattice with the element loop as one inline-asm block.
-// Written in C (the chromatic kernel above), the three-way kind branch is
-// restructured by the compiler into flow blocks whose joins move the
-// particle state between register sets: ~660 v_mov_b64 per wave on the
-// 58-element lattice, a third of its VALU instructions.  Here the state of
-// the four particles is tied in place ("+v"), and each element map updates
-// it in place with one temporary per particle (a plane at a time), so the
-// only moves are the two a 2x2 plane map needs (px, py).  The operations
-// and their order are those of el_drift_gen / el_quad_gen /
-// el_unified<false>, so the results equal the per-element path bitwise.
-//
-// Per element: the kind and the 13 achromatic coefficients of its record
-// are read with scalar loads (s[64:89]; kind s90) and waited for inside
-// the block; the record stride is kGen doubles.  No scalar stores.
-// Requires n_elem >= 1.
-static_assert(kGen == 24 && kDrift == 1 && kQuad == 2, "the asm loop hard-codes the record stride and kinds");
-
-#define HBL_G0 "s[64:65]"
-#define HBL_G1 "s[66:67]"
-#define HBL_G2 "s[68:69]"
-#define HBL_G3 "s[70:71]"
-#define HBL_G4 "s[72:73]"
-#define HBL_G5 "s[74:75]"
-#define HBL_G6 "s[76:77]"
-#define HBL_G7 "s[78:79]"
-#define HBL_G8 "s[80:81]"
-#define HBL_G9 "s[82:83]"
-#define HBL_G10 "s[84:85]"
-#define HBL_G11 "s[86:87]"
-#define HBL_G12 "s[88:89]"
-// one instruction "op d_k, c, s_k" for the four particles k = 0..3
-#define HBL_OP4(op, d, c, s)                                    \
-    op " %[" d "0], " c ", %[" s "0]\n\t" op " %[" d "1], " c ", %[" s "1]\n\t" \
-    op " %[" d "2], " c ", %[" s "2]\n\t" op " %[" d "3], " c ", %[" s "3]\n\t"
-#define HBL_MOV4(d, s)                                                              \
-    "v_mov_b64 %[" d "0], %[" s "0]\n\tv_mov_b64 %[" d "1], %[" s "1]\n\t"          \
-    "v_mov_b64 %[" d "2], %[" s "2]\n\tv_mov_b64 %[" d "3], %[" s "3]\n\t"
-#define HBL_MUL(d, c, s) HBL_OP4("v_mul_f64", d, c, s)
-#define HBL_FMA(d, c, s) HBL_OP4("v_fmac_f64", d, c, s)   // d += c * s (fused)
-
+// Achromatic fused lattice with the element loop as one inline-asm block
+// (HBL_ELEMENT_LOOP, hbl_elements.hpp) over the four particles of each
+// thread: no register copies at the kind-branch joins, results bitwise those
+// of the per-element path.  The chromatic form is k_lattice_fused<true> above.
 __global__ __launch_bounds__(kBlock) void k_lattice_fused_asm(double* __restrict__ z, int64_t n, int64_t ld,
                                                               const double* __restrict__ gen,
                                                               const int32_t* __restrict__ kinds, int32_t n_elem) {
@@ -254,52 +218,17 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused_asm(double* __restrict
         double w[kPer];
         uint32_t off = 0, koff = 0;     // byte offsets of the current record and kind
         int32_t cnt = n_elem;
-        asm volatile(
-            "L_elem_%=:\n\t"
-            "s_load_dword s90, %[kp], %[koff]\n\t"
-            "s_load_dwordx16 s[64:79], %[gp], %[off]\n\t"
-            "s_add_u32 s91, %[off], 0x40\n\t"
-            "s_load_dwordx8 s[80:87], %[gp], s91\n\t"
-            "s_add_u32 s91, %[off], 0x60\n\t"
-            "s_load_dwordx2 s[88:89], %[gp], s91\n\t"
-            "s_add_u32 %[off], %[off], 0xc0\n\t"
-            "s_add_u32 %[koff], %[koff], 4\n\t"
-            "s_waitcnt lgkmcnt(0)\n\t"
-            "s_cmp_eq_u32 s90, 1\n\t"
-            "s_cbranch_scc1 L_drift_%=\n\t"
-            "s_cmp_eq_u32 s90, 2\n\t"
-            "s_cbranch_scc1 L_quad_%=\n\t"
-            // unified record: t first (it reads the old x, px), then the x and y planes
-            HBL_FMA("t", HBL_G10, "x") HBL_FMA("t", HBL_G11, "px") HBL_FMA("t", HBL_G12, "pt")
-            HBL_MUL("w", HBL_G3, "x") HBL_MUL("x", HBL_G0, "x") HBL_FMA("w", HBL_G4, "px") HBL_FMA("x", HBL_G1, "px")
-            HBL_FMA("w", HBL_G5, "pt") HBL_FMA("x", HBL_G2, "pt") HBL_MOV4("px", "w")
-            HBL_MUL("w", HBL_G8, "y") HBL_MUL("y", HBL_G6, "y") HBL_FMA("w", HBL_G9, "py") HBL_FMA("y", HBL_G7, "py")
-            HBL_MOV4("py", "w")
-            "s_branch L_next_%=\n\t"
-            "L_drift_%=:\n\t"
-            HBL_FMA("x", HBL_G1, "px") HBL_FMA("y", HBL_G7, "py") HBL_FMA("t", HBL_G12, "pt")
-            "s_branch L_next_%=\n\t"
-            "L_quad_%=:\n\t"
-            HBL_MUL("w", HBL_G3, "x") HBL_MUL("x", HBL_G0, "x") HBL_FMA("w", HBL_G4, "px") HBL_FMA("x", HBL_G1, "px")
-            HBL_MOV4("px", "w")
-            HBL_MUL("w", HBL_G8, "y") HBL_MUL("y", HBL_G6, "y") HBL_FMA("w", HBL_G9, "py") HBL_FMA("y", HBL_G7, "py")
-            HBL_MOV4("py", "w")
-            HBL_FMA("t", HBL_G12, "pt")
-            "L_next_%=:\n\t"
-            "s_sub_u32 %[cnt], %[cnt], 1\n\t"
-            "s_cmp_lg_u32 %[cnt], 0\n\t"
-            "s_cbranch_scc1 L_elem_%="
-            : [x0] "+v"(p[0].x), [y0] "+v"(p[0].y), [t0] "+v"(p[0].t), [px0] "+v"(p[0].px), [py0] "+v"(p[0].py),
-              [x1] "+v"(p[1].x), [y1] "+v"(p[1].y), [t1] "+v"(p[1].t), [px1] "+v"(p[1].px), [py1] "+v"(p[1].py),
-              [x2] "+v"(p[2].x), [y2] "+v"(p[2].y), [t2] "+v"(p[2].t), [px2] "+v"(p[2].px), [py2] "+v"(p[2].py),
-              [x3] "+v"(p[3].x), [y3] "+v"(p[3].y), [t3] "+v"(p[3].t), [px3] "+v"(p[3].px), [py3] "+v"(p[3].py),
-              [w0] "=&v"(w[0]), [w1] "=&v"(w[1]), [w2] "=&v"(w[2]), [w3] "=&v"(w[3]),
-              [off] "+s"(off), [koff] "+s"(koff), [cnt] "+s"(cnt)
-            : [pt0] "v"(p[0].pt), [pt1] "v"(p[1].pt), [pt2] "v"(p[2].pt), [pt3] "v"(p[3].pt), [gp] "s"(gen),
-              [kp] "s"(kinds)
-            : "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71", "s72", "s73", "s74", "s75", "s76", "s77",
-              "s78", "s79", "s80", "s81", "s82", "s83", "s84", "s85", "s86", "s87", "s88", "s89", "s90", "s91", "scc",
-              "memory");
+        asm volatile(HBL_ELEMENT_LOOP(HBL_OP4, HBL_MOV4)
+                     : [x0] "+v"(p[0].x), [y0] "+v"(p[0].y), [t0] "+v"(p[0].t), [px0] "+v"(p[0].px),
+                       [py0] "+v"(p[0].py), [x1] "+v"(p[1].x), [y1] "+v"(p[1].y), [t1] "+v"(p[1].t),
+                       [px1] "+v"(p[1].px), [py1] "+v"(p[1].py), [x2] "+v"(p[2].x), [y2] "+v"(p[2].y),
+                       [t2] "+v"(p[2].t), [px2] "+v"(p[2].px), [py2] "+v"(p[2].py), [x3] "+v"(p[3].x),
+                       [y3] "+v"(p[3].y), [t3] "+v"(p[3].t), [px3] "+v"(p[3].px), [py3] "+v"(p[3].py),
+                       [w0] "=&v"(w[0]), [w1] "=&v"(w[1]), [w2] "=&v"(w[2]), [w3] "=&v"(w[3]),
+                       [off] "+s"(off), [koff] "+s"(koff), [cnt] "+s"(cnt)
+                     : [pt0] "v"(p[0].pt), [pt1] "v"(p[1].pt), [pt2] "v"(p[2].pt), [pt3] "v"(p[3].pt),
+                       [gp] "s"(gen), [kp] "s"(kinds)
+                     : HBL_ELEMENT_LOOP_CLOBBERS);
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = base + k * kBlock + threadIdx.x;
@@ -308,23 +237,6 @@ __global__ __launch_bounds__(kBlock) void k_lattice_fused_asm(double* __restrict
     }
 }
 
-#undef HBL_MUL
-#undef HBL_FMA
-#undef HBL_MOV4
-#undef HBL_OP4
-#undef HBL_G0
-#undef HBL_G1
-#undef HBL_G2
-#undef HBL_G3
-#undef HBL_G4
-#undef HBL_G5
-#undef HBL_G6
-#undef HBL_G7
-#undef HBL_G8
-#undef HBL_G9
-#undef HBL_G10
-#undef HBL_G11
-#undef HBL_G12
 
 // One element through its unified record: the unfused push of a lattice
 // with chromatic elements (the specialised kernels below are achromatic).
