@@ -93,6 +93,39 @@ def test_lattice58_fused_equals_unfused_and_oracle(hbl, orc):
     assert rel_err(g[:, cols], c).max() < TOL
 
 
+LATTICE_CASES = {
+    "drift": [W.drift(0.7)],
+    "quad": [W.quad(0.3, +1.7)],
+    "quad_defocus": [W.quad(0.3, -2.2)],
+    "sbend": [W.sbend(0.5, 5e-3)],
+    "lens": [W.lens(0.5)],
+    "quad_drift_runs": [W.quad(0.3, 2.0), W.quad(0.3, -2.0), W.drift(0.2), W.drift(0.3), W.lens(2.0),
+                        W.lens(-3.0), W.sbend(0.5, -5e-3), W.quad(0.3, 1.0)],
+}
+
+
+@pytest.mark.parametrize("case", sorted(LATTICE_CASES))
+@pytest.mark.parametrize("n", [1, 1023, 1025, 4097])
+def test_fused_single_kinds_and_runs(hbl, orc, case, n):
+    """The fused push's element loop on one element of each kind (a one-pass
+    loop), on runs of equal kinds, and on bunches that end inside a tile
+    (1024 particles per tile): equal to the per-element push bitwise and to
+    the oracle to 1e-12."""
+    line = LATTICE_CASES[case]
+    z, c = fill_pair(hbl, orc, n + 3, 77)
+    zu = z.clone()
+    ref = hbl.Ref.from_energy(1000.0)
+    lat = hbl.Lattice(line, ref)
+    lat.push(z, ref.copy(), fused=True, n=n)
+    lat.push(zu, ref.copy(), fused=False, n=n)
+    g, gu = to_host(z, n + 3), to_host(zu, n + 3)
+    assert np.array_equal(g, gu)
+    assert np.array_equal(g[:, n:], c[:, n:])                  # particles past n untouched
+    cn = np.ascontiguousarray(c[:, :n])
+    orc.push(cn, line, orc.Ref.from_energy(1000.0))
+    assert rel_err(g[:, :n], cn).max() < TOL
+
+
 def test_lattice58_full_size_sampled(hbl, orc):
     """The 58-element fused lattice on 2.5e7 particles (the largest size the
     benchmark times it at; 2.5e7 = 24,414 tiles of 1,024 + a 64-particle
