@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import rel_err
+from gpu_util import rel_err, to_dev
 from oracle import mlp_error as me
 from rounding_contract import SURROGATE
 
@@ -232,6 +232,43 @@ def test_gap_fused_passes_are_bitwise_equal(hbl):
     chain.run(zo, n=4096, stop_before_stage=1, record=zin, gaps_fused=False)
     torch.cuda.synchronize()
     assert torch.equal(ia[:, :4096], zin[:, :4096]) and torch.equal(oa[:, :4096], zo[:, :4096])
+
+
+@pytest.mark.parametrize("kind", ["drift", "quad", "sbend", "lens", "mixed"])
+def test_surrogate_gaps_single_kinds_bitwise(hbl, orc, kind):
+    """Surrogate inference with its entrance and exit gaps applied in
+    registers (the gaps' element loop) equals a lattice push, the plain
+    inference and a lattice push, bitwise, for one-element gaps of each
+    kind and a mixed gap; a bunch that ends inside a 64-particle group."""
+    torch = __import__("torch")
+    gaps = {"drift": [W.drift(0.4)], "quad": [W.quad(0.3, -1.5)], "sbend": [W.sbend(0.5, 5e-3)],
+            "lens": [W.lens(1.5)],
+            "mixed": [W.lens(2.0), W.drift(0.2), W.drift(0.3), W.quad(0.3, 2.0), W.sbend(0.5, -5e-3)]}[kind]
+    wl = W.c3_stage(n=8)
+    stage = wl.beamline[1]
+    m = 3001
+    x = orc.fill_gaussian(m, 31, (0.0,) * 6, wl.bunch.sigma)
+    sig = np.asarray(wl.bunch.sigma)
+    norm = np.concatenate([0.01 * sig, sig, 0.3 * sig, 1.7 * sig])
+    sur = hbl.Surrogate(5)
+    sur.set_norm(norm)
+    ref0 = hbl.Ref.from_energy(wl.E_MeV)
+    sur.set_stage(stage, ref0)
+    pre = hbl.Lattice(gaps, ref0)
+    ref_exit = ref0.copy()
+    ref_exit.gamma += stage.dE_MeV / ref_exit.mass_MeV
+    post = hbl.Lattice(gaps, ref_exit)
+    z1 = to_dev(x)
+    r1 = ref0.copy()
+    sur.apply(z1, r1, n=m, pre=pre, post=post)
+    z2 = to_dev(x)
+    r2 = ref0.copy()
+    pre.push(z2, r2, n=m)
+    sur.apply(z2, r2, n=m)
+    post.push(z2, r2, n=m)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
+    assert r1.gamma == r2.gamma and abs(r1.s - r2.s) < 1e-12
 
 
 def test_gap_lattice_energy_checked(hbl):
