@@ -333,6 +333,7 @@ def single_stage_study(args, log, chromatic=False):
     import torch
 
     import workloads as W
+    from paper_2402_17248_amd.chain import train_concurrently
     from paper_2402_17248_amd import hbl
 
     wl = W.c3_chromatic() if chromatic else W.c3_stage()
@@ -359,13 +360,15 @@ def single_stage_study(args, log, chromatic=False):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     sur.set_stage(stage, entry)
-    others = []                          # further init/shuffle seed sets on the same pairs
+    others = []                          # further init/shuffle seed sets on the same pairs, concurrently
     for sd in range(1, 1 if chromatic else args.seed_sets):
-        o = hbl.Surrogate(W.mlp_init_seed(0) + 1000 * sd)
-        o.train(zin, zout, npairs, batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR, lr_final=1e-5,
-                train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0) + 1000 * sd, keep_best=W.TRAIN_KEEP)
+        others.append((sd, hbl.Surrogate(W.mlp_init_seed(0) + 1000 * sd)))
+    train_concurrently([(o, zin, zout, npairs,
+                         dict(batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR, lr_final=1e-5,
+                              train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(0) + 1000 * sd,
+                              keep_best=W.TRAIN_KEEP)) for sd, o in others])
+    for _, o in others:
         o.set_stage(stage, entry)
-        others.append((sd, o))
     del zin, zout
 
     N = W.C4_INFER_N
@@ -726,24 +729,33 @@ def stage_accuracy_study(args, log, wl, chain):
     import workloads as W
     from paper_2402_17248_amd import hbl
 
+    from paper_2402_17248_amd.chain import train_concurrently
+
     n, sig = wl.bunch.n, wl.bunch.sigma
     seeds = list(range(args.seed_sets))
+    # the further seed sets' networks of every stage, trained at the same time
+    extra, jobs, pairs = {}, [], {}
+    for k in range(chain.stage_count if len(seeds) > 1 else 0):
+        pairs[k] = chain.make_pairs(k, args.pairs, W.c5_pair_seed(k + 1), sig)
+        for sd in seeds[1:]:
+            extra[(k, sd)] = hbl.Surrogate(W.mlp_init_seed(k + 1) + 1000 * sd)
+            jobs.append((extra[(k, sd)], *pairs[k], args.pairs,
+                         dict(batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR, lr_final=1e-5,
+                              train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(k + 1) + 1000 * sd,
+                              keep_best=W.TRAIN_KEEP)))
+    t0 = time.perf_counter()
+    train_concurrently(jobs)
+    if jobs:
+        log(f"seed-set networks: {len(jobs)} trained concurrently in {time.perf_counter() - t0:.1f} s")
+    del jobs, pairs
     out = []
     for k in range(chain.stage_count):
         zin, zout = chain.make_pairs(k, n, wl.bunch.seed, sig)
         stage, entry = chain.stage(k), chain.entry_ref(k)
         nets = {0: chain.surrogates[k]}
-        pin = pout = None
         for sd in seeds[1:]:
-            if pin is None:
-                pin, pout = chain.make_pairs(k, args.pairs, W.c5_pair_seed(k + 1), sig)
-            sur = hbl.Surrogate(W.mlp_init_seed(k + 1) + 1000 * sd)
-            sur.train(pin, pout, args.pairs, batch=W.TRAIN_BATCH, epochs=args.epochs, lr=W.TRAIN_LR,
-                      lr_final=1e-5, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(k + 1) + 1000 * sd,
-                      keep_best=W.TRAIN_KEEP)
-            sur.set_stage(stage, entry)
-            nets[sd] = sur
-        del pin, pout
+            extra[(k, sd)].set_stage(stage, entry)
+            nets[sd] = extra[(k, sd)]
         row = {"stage": k + 1, "particles": n, "by_seed_set": {}}
         for sd, sur in nets.items():
             zs = zin.clone()

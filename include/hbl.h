@@ -33,11 +33,13 @@
  *  - Handles (lattice, surrogate) own small device buffers on the device that
  *    was current when they were created; use them with that device current.
  *    A handle must not be used by two threads at once.
- *  - The reductions (hbl_moments, hbl_moments_async, hbl_compare) share one
- *    workspace per device, grown on demand and kept until the process ends:
- *    reductions that could run at the same time (enqueued on different
- *    streams, or from different threads) race on it, so keep them on one
- *    stream.
+ *  - The reductions (hbl_moments, hbl_moments_async, hbl_compare, and the
+ *    normalisation statistics of hbl_surrogate_train) use a workspace of
+ *    the stream they are enqueued on (one per device and stream, grown on
+ *    demand and kept until the process ends): reductions on one stream run
+ *    in order on its workspace, reductions on different streams use
+ *    different ones and may overlap.  Calls on one stream from several host
+ *    threads must not overlap.
  */
 #ifndef HBL_H
 #define HBL_H
@@ -199,7 +201,7 @@ hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out
  * array and nothing in it needs clearing between calls: two calls that can
  * overlap on one device (different streams, or different threads) race on
  * it, so keep them on one stream.  The scratch is not shared with the other
- * reductions' workspace. */
+ * reductions' workspaces. */
 hbl_status hbl_moments_async_noalloc(const double* z, int64_t n, int64_t ld, double* out27,
                                      hbl_stream stream);
 /* Host only.  Geometric RMS emittances of (x,px), (y,py), (t,pt),
@@ -298,7 +300,10 @@ hbl_status hbl_surrogate_set_stage(hbl_surrogate* m, const hbl_element* stage, c
  * entirely on the device (forward, MSE, backward, Adam and the per-epoch test
  * loss are this library's kernels).  SYNC at the end.  loss_log (host,
  * nullable, 2*epochs floats): mean training-batch loss and test loss per
- * epoch, in normalised units. */
+ * epoch, in normalised units.  Every buffer it uses is the handle's, its own
+ * or its stream's, so trainings of different handles on different streams
+ * (from different host threads) may run at the same time; each gives the
+ * result it gives alone. */
 hbl_status hbl_surrogate_train(hbl_surrogate* m, const double* zin, const double* zout, int64_t n_pairs,
                                int64_t ld, const hbl_train_cfg* cfg, float* loss_log, hbl_stream stream);
 

@@ -5,9 +5,45 @@ or, when a surrogate is attached, by the surrogate (§2: the hybrid
 conventional + surrogate beamline)."""
 from __future__ import annotations
 
-from typing import List, Optional
+from typing import List, Optional, Sequence
 
 from . import hbl
+
+
+def train_concurrently(jobs: Sequence, max_workers: int = 4):
+    """Train several networks at once.  jobs: (network, inputs, outputs,
+    n_pairs, keyword arguments of its train()).  Each training runs on a
+    stream of its own, driven by a host thread of its own (the library call
+    is synchronous and releases the interpreter): one batch-4096 step keeps
+    only 64 workgroups busy, so independent trainings overlap on the GPU,
+    and each one's host-side epoch shuffles run on their own core.  Every
+    training is deterministic and touches only its own buffers, so the
+    results equal those of sequential training bitwise.  The pairs must
+    have been written on the current stream; the streams wait for it.
+    Returns the loss curves in job order."""
+    import ctypes
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    if not jobs:
+        return []
+    main = torch.cuda.current_stream()
+    device = torch.cuda.current_device()
+    streams = [torch.cuda.Stream() for _ in jobs]
+    for st in streams:
+        st.wait_stream(main)
+
+    def run(j):
+        net, zin, zout, n_pairs, kw = jobs[j]
+        torch.cuda.set_device(device)
+        with torch.cuda.stream(streams[j]):
+            return net.train(zin, zout, n_pairs, stream=ctypes.c_void_p(streams[j].cuda_stream), **kw)
+
+    with ThreadPoolExecutor(max_workers=max(1, min(max_workers, len(jobs)))) as ex:
+        curves = list(ex.map(run, range(len(jobs))))
+    for st in streams:
+        main.wait_stream(st)
+    return curves
 
 
 class Chain:
@@ -61,24 +97,33 @@ class Chain:
 
     def train_surrogates(self, n_pairs: int, sigma, pair_seed, init_seed, shuffle_seed, epochs: int,
                          batch=4096, lr=1e-3, lr_final=1e-5, train_frac=0.7, stages=None, log=None,
-                         keep_best=False):
+                         keep_best=False, concurrent=True):
         """Train one surrogate per stage, each on its own pairs (the paper
         trains one network per stage, §4.2).  Seeds are callables of the
-        1-based stage number.  keep_best: each network ends with the
-        parameters of its lowest test loss."""
-        logs = []
-        for k in (range(self.stage_count) if stages is None else stages):
-            zin, zout = self.make_pairs(k, n_pairs, pair_seed(k + 1), sigma)
-            sur = hbl.Surrogate(init_seed(k + 1))
-            curve = sur.train(zin, zout, n_pairs, batch=batch, epochs=epochs, lr=lr, lr_final=lr_final,
-                              train_frac=train_frac, shuffle_seed=shuffle_seed(k + 1), keep_best=keep_best)
-            sur.set_stage(self.stage(k), self.entry_ref(k))
-            self.surrogates[k] = sur
-            logs.append(curve)
+        1-based stage number.  keep_best: as in Surrogate.train.
+        concurrent: the stages' trainings run at the same time on streams
+        of their own (train_concurrently; bitwise the same networks),
+        otherwise one after another."""
+        ks = list(range(self.stage_count) if stages is None else stages)
+        kw = lambda k: dict(batch=batch, epochs=epochs, lr=lr, lr_final=lr_final, train_frac=train_frac,
+                            shuffle_seed=shuffle_seed(k + 1), keep_best=keep_best)
+        surs = {k: hbl.Surrogate(init_seed(k + 1)) for k in ks}
+        if concurrent:
+            pairs = {k: self.make_pairs(k, n_pairs, pair_seed(k + 1), sigma) for k in ks}
+            curves = train_concurrently([(surs[k], *pairs[k], n_pairs, kw(k)) for k in ks])
+            del pairs
+        else:
+            curves = []
+            for k in ks:
+                zin, zout = self.make_pairs(k, n_pairs, pair_seed(k + 1), sigma)
+                curves.append(surs[k].train(zin, zout, n_pairs, **kw(k)))
+                del zin, zout
+        for k, curve in zip(ks, curves):
+            surs[k].set_stage(self.stage(k), self.entry_ref(k))
+            self.surrogates[k] = surs[k]
             if log:
                 log(f"stage {k + 1}: trained {epochs} epochs, final (train, test) loss {curve[-1].tolist()}")
-            del zin, zout
-        return logs
+        return curves
 
     def passes(self):
         """Group the segments into bunch passes: each stage absorbs the lattice

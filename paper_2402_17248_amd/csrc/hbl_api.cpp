@@ -36,8 +36,9 @@ void clear_error() { g_err[0] = 0; }
 namespace {
 constexpr int kMaxDev = 64;
 std::mutex g_mu;
-double* g_ws[kMaxDev] = {};
-size_t g_ws_bytes[kMaxDev] = {};
+// reduction workspaces, one per (device, stream): {buffer, bytes}
+std::map<std::pair<int, uintptr_t>, std::pair<double*, size_t>> g_ws;
+constexpr size_t kMaxWorkspaces = 256;
 
 struct StageKey {
     double g_in, gp, h;
@@ -55,21 +56,36 @@ int current_device() {
 }
 }  // namespace
 
-double* workspace(size_t bytes) {
+// The reduction workspace of stream s on the current device, grown on demand
+// and kept until the process ends.  Work on one stream runs in order, so the
+// stream's reductions reuse its buffer; reductions on different streams get
+// different buffers and never race.  Growing waits for the stream's earlier
+// work (which may still read the old buffer) before freeing it; past
+// kMaxWorkspaces buffers the device is synchronised and all are released.
+double* workspace(size_t bytes, hipStream_t s) {
     const int d = current_device();
     if (d < 0 || d >= kMaxDev) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_ws_bytes[d] < bytes) {
-        if (g_ws[d]) (void)hipFree(g_ws[d]);
-        g_ws[d] = nullptr;
-        g_ws_bytes[d] = 0;
-        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    const auto key = std::make_pair(d, (uintptr_t)s);
+    auto it = g_ws.find(key);
+    if (it == g_ws.end() && g_ws.size() >= kMaxWorkspaces) {
+        if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+        for (auto& kv : g_ws) (void)hipFree(kv.second.first);
+        g_ws.clear();
+    }
+    auto& e = g_ws[key];
+    if (e.second < bytes) {
+        if (e.first) {
+            if (hipStreamSynchronize(s) != hipSuccess) return nullptr;
+            (void)hipFree(e.first);
+        }
+        e = {nullptr, 0};
+        const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
         void* p = nullptr;
         if (hipMalloc(&p, want) != hipSuccess) return nullptr;
-        g_ws[d] = static_cast<double*>(p);
-        g_ws_bytes[d] = want;
+        e = {static_cast<double*>(p), want};
     }
-    return g_ws[d];
+    return e.first;
 }
 
 // gamma_ref at the middle of each substep of a stage, then the ramp increment
@@ -664,7 +680,7 @@ hbl_status hbl_moments_async(const double* z, int64_t n, int64_t ld, double* out
     HBL_REQUIRE(out27 && ((uintptr_t)out27 & 7u) == 0, "moments: bad output pointer");
     if (hbl_status st = check_device(z, bunch_bytes(n, ld), "moments")) return st;
     if (hbl_status st = check_device(out27, 27 * sizeof(double), "moments output")) return st;
-    double* ws = workspace(reduce_ws_bytes(n));
+    double* ws = workspace(reduce_ws_bytes(n), (hipStream_t)stream);
     if (!ws) { set_error(HBL_ENOMEM, "moments: workspace allocation failed"); return HBL_ENOMEM; }
     HBL_HIP(launch_moments(z, n, ld, ws, out27, (hipStream_t)stream));
     return HBL_OK;
@@ -694,10 +710,10 @@ hbl_status hbl_moments(const double* z, int64_t n, int64_t ld, double mean6[6], 
     HBL_REQUIRE(mean6 && cov21, "moments: NULL output");
     if (hbl_status st = check_device(z, bunch_bytes(n, ld), "moments")) return st;
     const size_t wsb = reduce_ws_bytes(n) + 64 * sizeof(double);
-    double* ws = workspace(wsb);
+    hipStream_t s = (hipStream_t)stream;
+    double* ws = workspace(wsb, s);
     if (!ws) { set_error(HBL_ENOMEM, "moments: workspace allocation failed"); return HBL_ENOMEM; }
     double* dout = ws + (wsb / sizeof(double) - 64);
-    hipStream_t s = (hipStream_t)stream;
     HBL_HIP(launch_moments(z, n, ld, ws, dout, s));
     double host[27];
     HBL_HIP(hipMemcpyAsync(host, dout, sizeof host, hipMemcpyDeviceToHost, s));
@@ -746,10 +762,10 @@ hbl_status hbl_compare(const double* zs, const double* zf, int64_t n, int64_t ld
     if (hbl_status st = hbl_moments(zs, n, ld, ms, cs, stream)) return st;
     if (hbl_status st = hbl_moments(zf, n, ld, mf, cf, stream)) return st;
     const size_t wsb = reduce_ws_bytes(n) + 64 * sizeof(double);
-    double* ws = workspace(wsb);
+    hipStream_t s = (hipStream_t)stream;
+    double* ws = workspace(wsb, s);
     if (!ws) { set_error(HBL_ENOMEM, "compare: workspace allocation failed"); return HBL_ENOMEM; }
     double* dout = ws + (wsb / sizeof(double) - 64);
-    hipStream_t s = (hipStream_t)stream;
     HBL_HIP(launch_diff2(zs, zf, n, ld, ws, dout, s));
     double d2[6];
     HBL_HIP(hipMemcpyAsync(d2, dout, sizeof d2, hipMemcpyDeviceToHost, s));

@@ -190,7 +190,8 @@ hipError_t launch_dense_adam_pack(float* p, float* m, float* v, const float* g, 
                                   float b1, float b2, float eps, const DenseShape& sh, const DenseImage& im,
                                   uint16_t* const* wt, hipStream_t s);
 
-// Per-device library workspace (grow-only, freed at exit).
-double* workspace(size_t bytes);
+// The reduction workspace of stream s on the current device (one buffer per
+// device and stream, grow-only, kept until the process ends).
+double* workspace(size_t bytes, hipStream_t s);
 
 }  // namespace hbl

@@ -121,6 +121,50 @@ def test_moments_async_matches_sync(hbl):
     assert out.cpu().tolist() == m + c
 
 
+def test_reductions_on_two_streams_do_not_share_a_workspace(hbl):
+    """Reductions enqueued on different streams at the same time (each stream
+    has a workspace of its own) give exactly the results of one-at-a-time
+    reductions: asynchronous moments of two bunches on two streams, repeated
+    so that the launches overlap, and synchronous moments from two host
+    threads."""
+    import threading
+    torch = __import__("torch")
+    n = 4_000_001
+    sig = W.BunchSpec(1, 1).sigma
+    za, zb = hbl.new_bunch(n), hbl.new_bunch(n)
+    hbl.fill_gaussian(za, 11, (0.0,) * 6, sig, n=n)
+    hbl.fill_gaussian(zb, 12, (1e-6,) * 6, sig, n=n)
+    want_a, want_b = hbl.moments(za, n=n), hbl.moments(zb, n=n)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    for st in (sa, sb):
+        st.wait_stream(torch.cuda.current_stream())
+    outs = [(torch.empty(27, dtype=torch.float64, device="cuda"), torch.empty(27, dtype=torch.float64, device="cuda"))
+            for _ in range(8)]
+    for oa, ob in outs:
+        with torch.cuda.stream(sa):
+            hbl.moments_async(za, oa, n=n, stream=hbl.C.c_void_p(sa.cuda_stream))
+        with torch.cuda.stream(sb):
+            hbl.moments_async(zb, ob, n=n, stream=hbl.C.c_void_p(sb.cuda_stream))
+    torch.cuda.synchronize()
+    for oa, ob in outs:
+        assert oa.cpu().tolist() == want_a[0] + want_a[1]
+        assert ob.cpu().tolist() == want_b[0] + want_b[1]
+    got = {}
+
+    def sync_moments(key, z, st):
+        torch.cuda.set_device(0)
+        with torch.cuda.stream(st):
+            got[key] = [hbl.moments(z, n=n, stream=hbl.C.c_void_p(st.cuda_stream)) for _ in range(4)]
+
+    th = [threading.Thread(target=sync_moments, args=("a", za, sa)),
+          threading.Thread(target=sync_moments, args=("b", zb, sb))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert all(r == want_a for r in got["a"]) and all(r == want_b for r in got["b"])
+
+
 def test_compare_full_size_constant_shift(hbl):
     """Properties that hold at any size, checked at 2.5e7 particles (the
     benchmark bunch; 95 particles per thread, so the four-at-a-time loop,

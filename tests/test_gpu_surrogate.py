@@ -385,3 +385,25 @@ def test_resume_after_save_and_load(hbl, orc, pairs):
     with pytest.raises(hbl.HblError) as ei:
         e.train(rec, out, n, epochs=1, resume=True, **cfg)
     assert ei.value.status == hbl.HBL_EINVAL and "whole number of epochs" in str(ei.value)
+
+
+def test_concurrent_training_equals_sequential(hbl, pairs):
+    """Several trainings at once, each on a stream and host thread of its own
+    (train_concurrently, as the staged chain trains its stages), give the
+    networks, normalisations and loss curves of one-after-another training
+    bitwise, for each model-selection mode."""
+    from paper_2402_17248_amd.chain import train_concurrently
+    n, rec, out, _, _, _, _ = pairs
+    kws = [dict(batch=512, epochs=4, lr=1e-3, lr_final=1e-4, train_frac=0.7, shuffle_seed=10 + j, keep_best=kb)
+           for j, kb in enumerate((0, 1, 2))]
+    seq = []
+    for j, kw in enumerate(kws):
+        s = hbl.Surrogate(20 + j)
+        curve = s.train(rec, out, n, **kw)
+        seq.append((s.get_params(), s.get_norm(), curve))
+    nets = [hbl.Surrogate(20 + j) for j in range(len(kws))]
+    curves = train_concurrently([(nets[j], rec, out, n, kws[j]) for j in range(len(kws))])
+    for j in range(len(kws)):
+        assert np.array_equal(nets[j].get_params(), seq[j][0]), j
+        assert np.array_equal(np.asarray(nets[j].get_norm()), np.asarray(seq[j][1])), j
+        assert np.array_equal(curves[j], seq[j][2]), j
