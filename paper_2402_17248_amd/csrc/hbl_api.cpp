@@ -121,11 +121,8 @@ static const double* stage_table(double g_in, double gp, double h, int32_t nsub,
         set_error(HBL_EHIP, "stage table upload failed: %s", hipGetErrorString(e));
         return nullptr;
     }
-    if (g_stage_tables[d].size() > 256) {  // bounded cache: drop everything
-        (void)hipDeviceSynchronize();
-        for (auto& kv : g_stage_tables[d]) (void)hipFree(kv.second);
-        g_stage_tables[d].clear();
-    }
+    // kept until the process ends (2 nsub doubles per distinct stage): a table
+    // handed to one thread may still be in use by work it has enqueued
     g_stage_tables[d][key] = static_cast<double*>(p);
     return static_cast<double*>(p);
 }
