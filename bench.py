@@ -646,21 +646,24 @@ def paper_shape_chain(args, log, wl, time_chain, dt_fine, z_fine):
 
     import workloads as W
     from paper_2402_17248_amd import hbl
-    from paper_2402_17248_amd.chain import Chain
+    from paper_2402_17248_amd.chain import Chain, train_concurrently
 
     c = Chain(wl.beamline, wl.E_MeV)
     n = wl.bunch.n
     t0 = time.perf_counter()
+    # the four stages' networks trained at the same time, each on its own stream
+    pairs = [c.make_pairs(k, args.pairs, W.c5_pair_seed(k + 1), wl.bunch.sigma) for k in range(c.stage_count)]
+    nets = [hbl.PreluNet(700, 3, W.mlp_init_seed(k + 1)) for k in range(c.stage_count)]
+    curves = train_concurrently([(nets[k], *pairs[k], args.pairs,
+                                  dict(batch=PAPER_BATCH, epochs=args.prelu_epochs // 2, lr=PAPER_LR,
+                                       lr_final=PAPER_LR / 10, train_frac=W.TRAIN_FRAC,
+                                       shuffle_seed=W.shuffle_seed(k + 1))) for k in range(c.stage_count)])
+    del pairs
     losses = []
-    for k in range(c.stage_count):
-        zin, zout = c.make_pairs(k, args.pairs, W.c5_pair_seed(k + 1), wl.bunch.sigma)
-        net = hbl.PreluNet(700, 3, W.mlp_init_seed(k + 1))
-        curve = net.train(zin, zout, args.pairs, batch=PAPER_BATCH, epochs=args.prelu_epochs // 2, lr=PAPER_LR,
-                          lr_final=PAPER_LR / 10, train_frac=W.TRAIN_FRAC, shuffle_seed=W.shuffle_seed(k + 1))
+    for k, (net, curve) in enumerate(zip(nets, curves)):
         net.set_stage(c.stage(k), c.entry_ref(k))
         c.surrogates[k] = net
         losses.append([float(v) for v in curve[-1]])
-        del zin, zout
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     dt = time_chain(lambda zz: c.run(zz, n=n, use_surrogates=True), 3, 1)

@@ -173,3 +173,23 @@ def test_save_load_roundtrip(hbl, orc, pairs, tmp_path):
     open(path, "wb").write(bytes(raw))
     with pytest.raises(hbl.HblError):
         hbl.PreluNet.load(path)
+
+
+def test_concurrent_training_equals_sequential(hbl, pairs):
+    """PReLU networks trained at the same time on streams of their own
+    (train_concurrently) equal one-after-another training bitwise."""
+    from paper_2402_17248_amd.chain import train_concurrently
+    n, rec, out, _, _ = pairs
+    shapes = [(136, 2), (72, 3), (100, 1)]
+    kws = [dict(batch=500, epochs=2, lr=1e-3, lr_final=1e-4, shuffle_seed=30 + j) for j in range(len(shapes))]
+    seq = []
+    for j, (w, h) in enumerate(shapes):
+        net = hbl.PreluNet(w, h, 40 + j)
+        curve = net.train(rec, out, n, **kws[j])
+        seq.append((net.get_params(), net.get_norm(), curve))
+    nets = [hbl.PreluNet(w, h, 40 + j) for j, (w, h) in enumerate(shapes)]
+    curves = train_concurrently([(nets[j], rec, out, n, kws[j]) for j in range(len(shapes))])
+    for j in range(len(shapes)):
+        assert np.array_equal(nets[j].get_params(), seq[j][0]), j
+        assert nets[j].get_norm() == seq[j][1], j
+        assert np.array_equal(curves[j], seq[j][2]), j
