@@ -27,6 +27,8 @@ def train_concurrently(jobs: Sequence, max_workers: int = 4):
     import torch
     if not jobs:
         return []
+    if len({id(j[0]) for j in jobs}) != len(jobs):
+        raise ValueError("train_concurrently: a network appears in more than one job")
     main = torch.cuda.current_stream()
     device = torch.cuda.current_device()
     streams = [torch.cuda.Stream() for _ in jobs]

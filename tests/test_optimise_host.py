@@ -63,3 +63,19 @@ def test_general_sections_reach_a_waist_and_pick_the_small_one():
 def test_twiss_from_moments_round_trip():
     b, a, e = twiss_from_moments(cov21_of(0.7, -2.0, 3e-8))
     assert (b, a, e) == pytest.approx((0.7, -2.0, 3e-8), rel=1e-12)
+
+
+def test_train_concurrently_rejects_a_shared_network():
+    """Two jobs on one network handle would race on its buffers: rejected
+    before anything runs (no GPU needed)."""
+    import pytest
+    from paper_2402_17248_amd.chain import train_concurrently
+
+    class Net:
+        def train(self, *a, **k):
+            raise AssertionError("must not run")
+
+    net = Net()
+    with pytest.raises(ValueError, match="more than one job"):
+        train_concurrently([(net, None, None, 0, {}), (net, None, None, 0, {})])
+    assert train_concurrently([]) == []
