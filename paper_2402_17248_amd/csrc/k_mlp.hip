@@ -152,6 +152,7 @@ struct NormArgs {
     double mu_out[6];
     double sd_out[6];
 };
+typedef __attribute__((address_space(4))) const NormArgs cNormArgs;
 
 // Network state resident in registers for the whole kernel.
 struct Net {
@@ -253,7 +254,7 @@ constexpr int kInferBlock = 256;
 // rows 4-5 in lane group 1) -- cross-lane moves only, no redundant loads.
 template <bool GAPS, bool CHROM = false>
 __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(
-    double* __restrict__ z, int64_t n, int64_t ld, const uint32_t* __restrict__ img, NormArgs na,
+    NormArgs, double* __restrict__ z, int64_t n, int64_t ld, const uint32_t* __restrict__ img,
     LatticeView pre, LatticeView post) {
     Net net;
     load_net(img, net);
@@ -261,6 +262,13 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
     const int64_t waves = (int64_t)gridDim.x * (kInferBlock / 64);
     const int64_t wave = (int64_t)blockIdx.x * (kInferBlock / 64) + (threadIdx.x >> 6);
     for (int64_t base = wave * 64; base < n; base += waves * 64) {
+        // The normalisation constants (the first kernel argument, at offset 0 of the
+        // argument segment) are re-read from that segment each iteration through a
+        // pointer the compiler cannot follow: held in 48 scalar registers across the
+        // loop they are spilled to vector lanes and restored one readlane at a time.
+        cNormArgs* np = (cNormArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(np));
+        cNormArgs& na = *np;
         const int64_t i = base + l;
         const bool live = i < n;
         P6 p;
@@ -878,13 +886,13 @@ hipError_t launch_mlp_infer(double* z, int64_t n, int64_t ld, const uint32_t* im
     const int64_t cap = 256 * 2;  // persistent: two 4-wave blocks per CU
     if (blocks > cap) blocks = cap;
     if ((pre.n > 0 && pre.chromatic) || (post.n > 0 && post.chromatic))
-        hipLaunchKernelGGL((k_mlp_infer<true, true>), dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld,
-                           img, na, pre, post);
+        hipLaunchKernelGGL((k_mlp_infer<true, true>), dim3((unsigned)blocks), dim3(kInferBlock), 0, s, na, z, n,
+                           ld, img, pre, post);
     else if (pre.n > 0 || post.n > 0)
-        hipLaunchKernelGGL(k_mlp_infer<true>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na,
+        hipLaunchKernelGGL(k_mlp_infer<true>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, na, z, n, ld, img,
                            pre, post);
     else
-        hipLaunchKernelGGL(k_mlp_infer<false>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, z, n, ld, img, na,
+        hipLaunchKernelGGL(k_mlp_infer<false>, dim3((unsigned)blocks), dim3(kInferBlock), 0, s, na, z, n, ld, img,
                            pre, post);
     return hipGetLastError();
 }
