@@ -350,7 +350,8 @@ hbl_status hbl_surrogate_load(const char* path, hbl_surrogate** out);
  * the W x W layers and the output layer as bf16 products with FP32
  * accumulation on the matrix cores, bias and PReLU in FP32, each hidden
  * activation rounded to bf16; output FP32, de-normalised in FP64.
- * Device memory held by a network: its parameters, their bf16 image and two
+ * Device memory held by a network: its parameters, their bf16 image (for
+ * 512 <= W' <= 960 with a second, K-blocked copy of the W x W layers) and two
  * activation buffers of 65536 x W' bf16 (W' = W rounded up to 64; 2 x 126 MB
  * at W = 900), allocated at creation.  Calls that use one network must be
  * ordered (one stream, or synchronised): they share those buffers. */

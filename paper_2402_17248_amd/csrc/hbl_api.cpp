@@ -1489,11 +1489,12 @@ size_t prelu_image_layout(const hbl_mlp_shape* sh, DenseImage* im, char* base) {
     im->w0 = (float*)take(sizeof(float) * wp * 6);
     im->b0 = (float*)take(sizeof(float) * wp);
     im->slope = (float*)take(sizeof(float) * kDenseMaxHidden);
-    for (int l = 0; l <= kDenseMaxHidden; ++l) { im->w[l] = nullptr; im->b[l] = nullptr; }
+    for (int l = 0; l <= kDenseMaxHidden; ++l) { im->w[l] = nullptr; im->b[l] = nullptr; im->wb[l] = nullptr; }
     for (int l = 1; l <= sh->hidden; ++l) {
         const int64_t rows = l == sh->hidden ? 16 : wp;
         im->w[l] = (uint16_t*)take(sizeof(uint16_t) * rows * wp);
         im->b[l] = (float*)take(sizeof(float) * rows);
+        if (l < sh->hidden && dense_blocked((int)wp)) im->wb[l] = (uint16_t*)take(sizeof(uint16_t) * wp * wp);
     }
     return off;
 }

@@ -140,7 +140,13 @@ struct DenseImage {
     float* slope;                        // [hidden] PReLU slopes
     uint16_t* w[kDenseMaxHidden + 1];    // layer l >= 1: bf16 [wp][wp] (output layer [16][wp])
     float* b[kDenseMaxHidden + 1];       // layer l >= 1: [wp] (output layer [16])
+    // hidden layers 1 <= l < hidden again, K-blocked: [wp/32][wp][32] (element
+    // (o, k) at (k/32) wp 32 + 32 o + k % 32); nullptr unless dense_blocked(wp)
+    uint16_t* wb[kDenseMaxHidden + 1];
 };
+// Widths whose inference runs on K-blocked activations and weights (the
+// hidden layers as 4 M blocks of wp/4 rows on the direct-load kernel).
+bool dense_blocked(int wp);
 struct DenseNorm {
     double mu_in[6], sd_in[6], mu_out[6], sd_out[6];
 };

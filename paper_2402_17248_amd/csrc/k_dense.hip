@@ -12,6 +12,11 @@
 // particles are computed from a zero input and never written back.  Weights
 // of a W x W layer: [Wp][Wp] bf16 row-major ([out][in]) with zero padding;
 // the output layer: [16][Wp] (rows 6..15 zero); biases FP32, padded.
+// K-blocked layout (inference at 512 <= Wp <= 960, dense_blocked): the same
+// matrices cut into K chunks of 32, [Wp/32][rows][32], so that the 64 bytes
+// of one row in one chunk sit next to those of the following rows and the
+// operand loads of a chunk read whole 128-byte lines (row-major rows put
+// half a line in one chunk and the other half in the next).
 //
 // GEMM (layer l, D^T = W X^T): the out-features are the MFMA A operand
 // (rows), particles the B operand (columns), so a lane's 4 accumulators are
@@ -64,12 +69,13 @@ __device__ __forceinline__ void tile_of(int id, int mblocks, int& m, int& tile) 
 
 // ------------------------------------------------------------ packing
 __global__ void k_pack_bf16(const float* __restrict__ src, int rows, int cols, uint16_t* __restrict__ dst,
-                            int rows_p, int cols_p) {
+                            int rows_p, int cols_p, int blocked) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)rows_p * cols_p) return;
     const int r = (int)(i / cols_p), c = (int)(i % cols_p);
     const float v = (r < rows && c < cols) ? src[(int64_t)r * cols + c] : 0.0f;
-    dst[i] = __builtin_bit_cast(uint16_t, (__bf16)v);
+    const int64_t d = blocked ? (int64_t)(c >> 5) * rows_p * 32 + (int64_t)r * 32 + (c & 31) : i;
+    dst[d] = __builtin_bit_cast(uint16_t, (__bf16)v);
 }
 
 __global__ void k_pack_f32(const float* __restrict__ src, int n, float* __restrict__ dst, int n_p) {
@@ -86,10 +92,10 @@ __global__ void k_pack_f32(const float* __restrict__ src, int n, float* __restri
 // one activation row.
 constexpr int kInP = 256;
 
-template <bool GAPS, bool CHROM>
+template <bool GAPS, bool CHROM, bool BLK>
 __global__ __launch_bounds__(kBlock) void k_dense_input(const double* __restrict__ z, int64_t nend, int64_t ld,
                                                         int64_t p0, DenseImage im, DenseNorm nm,
-                                                        LatticeView pre, uint16_t* __restrict__ x) {
+                                                        LatticeView pre, uint16_t* __restrict__ x, int64_t rows) {
     __shared__ float xs[kInP][6];
     const int tid = threadIdx.x;
     {
@@ -118,7 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_input(const double* __restrict
         for (int c = 0; c < 6; ++c) w[j][c] = im.w0[(gq * 8 + j) * 6 + c];
     }
     const float a0 = im.slope[0];
-    uint16_t* xb = x + (int64_t)blockIdx.x * kInP * im.wp + gq * 8;
+    // row-major: row stride wp; K-blocked: features 8 gq .. 8 gq + 7 lie in
+    // chunk gq / 4 at offset 8 (gq % 4), row stride 32
+    const int64_t rstride = BLK ? 32 : im.wp;
+    uint16_t* xb = BLK ? x + (int64_t)(gq >> 2) * rows * 32 + (int64_t)blockIdx.x * kInP * 32 + (gq & 3) * 8
+                       : x + (int64_t)blockIdx.x * kInP * im.wp + gq * 8;
     for (int q = set; q < kInP; q += sets) {
         float h[8];
 #pragma unroll
@@ -128,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_input(const double* __restrict
             for (int c = 0; c < 6; ++c) acc = fmaf(w[j][c], xs[q][c], acc);
             h[j] = prelu(acc, a0);
         }
-        *(u32x4*)(xb + (int64_t)q * im.wp) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+        *(u32x4*)(xb + (int64_t)q * rstride) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
     }
 }
 
@@ -189,7 +199,7 @@ __device__ __forceinline__ void wait_vm() {
 // WM = 1: 4 waves, each with all MT row tiles of the M block and 64
 // particles; WM = 2: 8 waves (two per SIMD, so one can issue products while
 // the other waits), each with half the row tiles.
-template <int MT, int WM, int EPI, bool GAPS, bool CHROM>
+template <int MT, int WM, int EPI, bool GAPS, bool CHROM, bool BX = false>
 __global__ __launch_bounds__(256 * WM) __attribute__((amdgpu_waves_per_eu(WM, WM))) void k_dense_layer(
     LayerArgs a, DenseNorm nm, LatticeView post) {
     static_assert(MT % WM == 0, "the M block splits evenly over the wave rows");
@@ -231,7 +241,11 @@ __global__ __launch_bounds__(256 * WM) __attribute__((amdgpu_waves_per_eu(WM, WM
 #pragma unroll
         for (int i = 0; i < B_PER_WAVE; ++i) {
             const int j = wave * B_PER_WAVE + i;       // tile rows 16j .. 16j+15
-            dma_rows16(xt + (int64_t)(j * 16) * K, K, (j * 16) & 63, k0, B + j * 1024, lane);
+            if (BX)                                    // K-blocked X: 1 KB contiguous
+                dma_rows16(a.x + ((int64_t)kc * a.tiles * PROWS + (int64_t)tile * PROWS + j * 16) * 32, 32,
+                           (j * 16) & 63, 0, B + j * 1024, lane);
+            else
+                dma_rows16(xt + (int64_t)(j * 16) * K, K, (j * 16) & 63, k0, B + j * 1024, lane);
         }
     };
 
@@ -410,6 +424,112 @@ __global__ __launch_bounds__(256 * WM) __attribute__((amdgpu_waves_per_eu(WM, WM
                 if (GAPS) apply_elements<CHROM>(q, post);
                 store6(a.z, a.ld, i, q);
             }
+        }
+    }
+}
+
+
+// Hidden layer of inference on K-blocked X, W and Y, at MT = Wp/64 row tiles
+// per M block (4 M blocks).  Each wave's 64 particles are its own, so the
+// particle operand goes from global memory straight into registers (a ring
+// of 5 chunks, loads 3 chunks ahead) and only the M block's weights go
+// through LDS (direct-to-LDS, a ring of 4 stages shared by the four waves).
+// NK = Wp/32 K chunks, fixed at compile time: the loop is unrolled and every
+// ring slot is a constant.  Each accumulator takes its chunks in order, one
+// 16x16x32 product per chunk, as in k_dense_layer: the two kernels give the
+// same bits.
+constexpr int kBlkMinMT = 8, kBlkMaxMT = 15;
+template <int MT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dense_hidden_blk(LayerArgs a) {
+    constexpr int NK = 2 * MT, K = NK * kKc, ROWS = MT * 16, PROWS = kWaves * kNT * 16, A_BYTES = ROWS * 64;
+    constexpr int A_PER_WAVE = (MT + kWaves - 1) / kWaves, PER_CHUNK = A_PER_WAVE + kNT, BR = kStages + 1;
+    static_assert(MT <= kBlkMaxMT, "MT x 4 x 4 accumulators fit the 256 accumulator registers");
+    __shared__ __attribute__((aligned(1024))) char smem[kStages * A_BYTES];
+    int m, tile;
+    tile_of(blockIdx.x, a.mblocks, m, tile);
+    if (tile >= a.tiles) return;                        // whole workgroup: no barrier follows
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r = lane & 15;
+    const int64_t R = (int64_t)a.tiles * PROWS;         // rows of this launch's X and Y
+    const int64_t wrow0 = (int64_t)tile * PROWS + wave * (kNT * 16);
+    const uint16_t* xl = a.x + (wrow0 + r) * 32 + 8 * g;
+    const uint16_t* wm0 = a.w + (int64_t)m * ROWS * 32;
+    typedef __attribute__((address_space(3))) char lds_char;
+    lds_char* sm = (lds_char*)smem;
+    bf16x8 bq[BR][kNT];                                 // particle operands, chunk kc in slot kc % BR
+    bf16x8 aq[2][MT];                                   // weight operands of chunks kc (even/odd)
+    f32x4 acc[MT][kNT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto issue = [&](int kc) {
+        lds_char* A = sm + (kc % kStages) * A_BYTES;
+#pragma unroll
+        for (int i = 0; i < A_PER_WAVE; ++i) {
+            const int j = min(wave + i * kWaves, MT - 1);
+            dma_rows16(wm0 + ((int64_t)kc * K + j * 16) * 32, 32, j * 16, 0, A + j * 1024, lane);
+        }
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) bq[kc % BR][nt] = *(const bf16x8*)(xl + ((int64_t)kc * R + nt * 16) * 32);
+    };
+    auto read_a = [&](int kc) {
+        const lds_char* A = sm + (kc % kStages) * A_BYTES;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int ar = mt * 16 + r;
+            aq[kc & 1][mt] = *(const __attribute__((address_space(3))) bf16x8*)(A + ar * 64 + ((g ^ swz(ar)) * 16));
+        }
+    };
+    auto products = [&](int kc) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[kc & 1][mt], bq[kc % BR][nt], acc[mt][nt], 0, 0, 0);
+    };
+#pragma unroll
+    for (int kc = 0; kc < kStages - 1; ++kc)
+        if (kc < NK) issue(kc);
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        // chunk c readable: this wave's loads of it have landed (the loads of
+        // the chunks after it, up to c + kStages - 2, may be pending) and every
+        // wave's operand reads of chunk c - 1 are done, so its stage and its
+        // register slot take chunk c + kStages - 1
+        const int after = min(c + kStages - 2, NK - 1) - c;
+        if (after >= 2) wait_vm<2 * PER_CHUNK>();
+        else if (after == 1) wait_vm<PER_CHUNK>();
+        else wait_vm<0>();
+        __builtin_amdgcn_s_waitcnt(0xC07F);             // lgkmcnt(0) only
+        asm volatile("s_barrier" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        const bool more = c + kStages - 1 < NK;
+        if (more) issue(c + kStages - 1);
+        read_a(c);
+        if (c > 0) products(c - 1);
+        // the loads first, then each operand read of chunk c beside the kNT
+        // products of chunk c - 1 that use the register it replaces
+        if (more) __builtin_amdgcn_sched_group_barrier(0x010, PER_CHUNK, 0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            if (c > 0) __builtin_amdgcn_sched_group_barrier(0x008, kNT, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    products(NK - 1);
+    const float s = *a.slope;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int o = m * ROWS + mt * 16 + 4 * g;
+        const f32x4 bb = *(const f32x4*)(a.bias + o);
+        uint16_t* yo = a.y + ((int64_t)(o >> 5) * R + wrow0 + r) * 32 + (o & 31);
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+            const f32x4 v = acc[mt][nt];
+            const u32x2 st = {pack2(prelu(v[0] + bb[0], s), prelu(v[1] + bb[1], s)),
+                              pack2(prelu(v[2] + bb[2], s), prelu(v[3] + bb[3], s))};
+            *(u32x2*)(yo + nt * 16 * 32) = st;
         }
     }
 }
@@ -678,6 +798,7 @@ __global__ void k_dense_adam_pack(float* __restrict__ p, float* __restrict__ m, 
             const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pi);
             im.w[l][(int64_t)o * wp + k] = b;
             if (l < H && wt.w[l]) wt.w[l][(int64_t)k * wp + o] = b;
+            if (l < H && im.wb[l]) im.wb[l][(int64_t)(k >> 5) * wp * 32 + (int64_t)o * 32 + (k & 31)] = b;
         }
     }
 }
@@ -712,7 +833,18 @@ int hidden_mt(int wp) {
     return 1;
 }
 
+template <int MT>
+hipError_t launch_hidden_blk(const LayerArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_hidden_blk<MT>, dim3(layer_grid(a)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+constexpr LayerLauncher kHiddenBlk[kBlkMaxMT - kBlkMinMT + 1] = {
+    launch_hidden_blk<8>,  launch_hidden_blk<9>,  launch_hidden_blk<10>, launch_hidden_blk<11>,
+    launch_hidden_blk<12>, launch_hidden_blk<13>, launch_hidden_blk<14>, launch_hidden_blk<15>};
+
 }  // namespace
+
+bool dense_blocked(int wp) { return wp % 64 == 0 && wp / 64 >= kBlkMinMT && wp / 64 <= kBlkMaxMT; }
 
 hipError_t launch_dense_pack(const float* params, const DenseShape& sh, const DenseImage& im, hipStream_t s) {
     const int W = sh.width, Wp = im.wp, H = sh.hidden;
@@ -728,7 +860,10 @@ hipError_t launch_dense_pack(const float* params, const DenseShape& sh, const De
             const int rows_p = l == H ? 16 : Wp;
             const int64_t cnt = (int64_t)rows_p * Wp;
             hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, A, no, ni,
-                               im.w[l], rows_p, Wp);
+                               im.w[l], rows_p, Wp, 0);
+            if (l < H && im.wb[l])
+                hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, A, no, ni,
+                                   im.wb[l], rows_p, Wp, 1);
             hipLaunchKernelGGL(k_pack_f32, dim3((rows_p + 255) / 256), dim3(256), 0, s, b, no, im.b[l], rows_p);
         }
         off += (int64_t)no * (ni + 1);
@@ -749,26 +884,53 @@ hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape
     const int tile = dense_tile_rows();
     const bool gaps = pre.n > 0 || post.n > 0;
     const bool chrom = pre.chromatic || post.chromatic;
+    // 512 <= W' <= 960: activations K-blocked, hidden layers on k_dense_hidden_blk
+    const bool blk = dense_blocked(Wp);
+    for (int l = 1; l < H; ++l)
+        if (blk && !im.wb[l]) return hipErrorInvalidValue;
     for (int64_t p0 = 0; p0 < n; p0 += chunk) {
         const int64_t nc = n - p0 < chunk ? n - p0 : chunk, nend = p0 + nc;
         const int tiles = (int)((nc + tile - 1) / tile);
         const int64_t rows = (int64_t)tiles * tile;
         const dim3 gin((unsigned)(rows / kInP));
-        if (!gaps)
-            hipLaunchKernelGGL((k_dense_input<false, false>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im, nm, pre, buf0);
-        else if (!chrom)
-            hipLaunchKernelGGL((k_dense_input<true, false>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im, nm, pre, buf0);
-        else
-            hipLaunchKernelGGL((k_dense_input<true, true>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im, nm, pre, buf0);
+        if (blk) {
+            if (!gaps)
+                hipLaunchKernelGGL((k_dense_input<false, false, true>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im, nm,
+                                   pre, buf0, rows);
+            else if (!chrom)
+                hipLaunchKernelGGL((k_dense_input<true, false, true>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im, nm,
+                                   pre, buf0, rows);
+            else
+                hipLaunchKernelGGL((k_dense_input<true, true, true>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im, nm,
+                                   pre, buf0, rows);
+        } else {
+            if (!gaps)
+                hipLaunchKernelGGL((k_dense_input<false, false, false>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im,
+                                   nm, pre, buf0, rows);
+            else if (!chrom)
+                hipLaunchKernelGGL((k_dense_input<true, false, false>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im,
+                                   nm, pre, buf0, rows);
+            else
+                hipLaunchKernelGGL((k_dense_input<true, true, false>), gin, dim3(kBlock), 0, s, z, nend, ld, p0, im,
+                                   nm, pre, buf0, rows);
+        }
         uint16_t* xin = buf0;
         uint16_t* yout = buf1;
         for (int l = 1; l < H; ++l) {
             LayerArgs a{};
             a.x = xin; a.w = im.w[l]; a.bias = im.b[l]; a.slope = im.slope + l; a.y = yout;
             a.K = Wp; a.Mp = Wp; a.mblocks = Wp / (16 * MT); a.tiles = tiles;
-            // 12-tile M blocks (W' = 960 and other multiples of 192) take the
-            // 8-wave form: measured 9 % faster than 4 waves
-            hipError_t e = MT == 12 ? launch_layer_mt<12, kEpiHidden, 2>(a, s) : LayerTable<kEpiHidden>::f[MT - 1](a, s);
+            hipError_t e;
+            if (blk) {
+                a.w = im.wb[l];
+                a.mblocks = 4;
+                e = kHiddenBlk[Wp / 64 - kBlkMinMT](a, s);
+            } else {
+                // 12-tile M blocks (W' = 1024 and other multiples of 192 outside
+                // the blocked range) take the 8-wave form: measured 9 % faster
+                // than 4 waves
+                e = MT == 12 ? launch_layer_mt<12, kEpiHidden, 2>(a, s) : LayerTable<kEpiHidden>::f[MT - 1](a, s);
+            }
             if (e != hipSuccess) return e;
             uint16_t* t = xin; xin = yout; yout = t;
         }
@@ -776,7 +938,17 @@ hipError_t launch_dense_infer(double* z, int64_t n, int64_t ld, const DenseShape
         a.x = xin; a.w = im.w[H]; a.bias = im.b[H]; a.K = Wp; a.Mp = 16; a.mblocks = 1; a.tiles = tiles;
         a.z = z; a.ld = ld; a.p0 = p0; a.nend = nend;
         const dim3 gout((unsigned)(((tiles + 7) / 8) * 8));
-        if (!gaps)
+        if (blk) {
+            if (!gaps)
+                hipLaunchKernelGGL((k_dense_layer<1, 1, kEpiOut, false, false, true>), gout, dim3(kBlock), 0, s, a, nm,
+                                   post);
+            else if (!chrom)
+                hipLaunchKernelGGL((k_dense_layer<1, 1, kEpiOut, true, false, true>), gout, dim3(kBlock), 0, s, a, nm,
+                                   post);
+            else
+                hipLaunchKernelGGL((k_dense_layer<1, 1, kEpiOut, true, true, true>), gout, dim3(kBlock), 0, s, a, nm,
+                                   post);
+        } else if (!gaps)
             hipLaunchKernelGGL((k_dense_layer<1, 1, kEpiOut, false, false>), gout, dim3(kBlock), 0, s, a, nm, post);
         else if (!chrom)
             hipLaunchKernelGGL((k_dense_layer<1, 1, kEpiOut, true, false>), gout, dim3(kBlock), 0, s, a, nm, post);

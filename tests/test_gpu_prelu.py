@@ -79,12 +79,16 @@ def test_forward_parity_paper_shapes(hbl, orc, width, hidden):
     assert mx < 5e-3 and med < 1e-7 and frac < 0.01
 
 
-@pytest.mark.parametrize("m", [1, 255, 256, 257, 65536 + 300])
-def test_forward_ragged_and_chunked(hbl, orc, m):
-    sh = orc.shape(width=100, hidden=2)
+@pytest.mark.parametrize("width,m", [(100, 1), (100, 255), (100, 256), (100, 257), (100, 65536 + 300),
+                                     (520, 1), (520, 257), (520, 65536 + 300)])
+def test_forward_ragged_and_chunked(hbl, orc, width, m):
+    """Ragged tiles and several chunks, on row-major activations (W' = 128)
+    and on K-blocked ones (W' = 576), where a chunk's rows set the stride of
+    the blocks."""
+    sh = orc.shape(width=width, hidden=2)
     x, norm = bunch(orc, m + 5, 22)
     p = perturbed(orc, sh, 8)
-    net = hbl.PreluNet(100, 2, 0)
+    net = hbl.PreluNet(width, 2, 0)
     net.set_params(p)
     net.set_norm(norm)
     z = to_dev(x)
@@ -97,12 +101,14 @@ def test_forward_ragged_and_chunked(hbl, orc, m):
     assert np.array_equal(g[:, m:], x[:, m:])          # particles past n untouched
 
 
-def test_gaps_equal_separate_calls(hbl, orc):
-    """pre lattice, network, post lattice in the same launches == three calls (bitwise)."""
+@pytest.mark.parametrize("width", [128, 520])
+def test_gaps_equal_separate_calls(hbl, orc, width):
+    """pre lattice, network, post lattice in the same launches == three calls
+    (bitwise), on row-major and on K-blocked activations."""
     m = 3000
     wl = W.c3_chromatic(n=8)
     x, norm = bunch(orc, m, 23)
-    net = hbl.PreluNet(128, 2, 3)
+    net = hbl.PreluNet(width, 2, 3)
     net.set_norm(norm)
     stage = wl.beamline[1]
     for chromatic in (False, True):

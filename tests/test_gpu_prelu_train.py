@@ -175,6 +175,24 @@ def test_save_load_roundtrip(hbl, orc, pairs, tmp_path):
         hbl.PreluNet.load(path)
 
 
+@pytest.mark.parametrize("width", [136, 520])
+def test_inference_after_training_equals_repacked(hbl, pairs, width):
+    """Training writes each updated weight into every operand image the
+    network keeps (row-major, transposed and, at 512 <= W' <= 960, the
+    K-blocked copy that inference reads): inference right after training
+    equals, bit for bit, that of a network given the same parameters afresh."""
+    n, rec, out, _, _ = pairs
+    net = hbl.PreluNet(width, 2, 5)
+    net.train(rec, out, n, batch=500, epochs=1, lr=1e-3, shuffle_seed=3)
+    fresh = hbl.PreluNet(width, 2, 6)
+    fresh.set_params(net.get_params())
+    fresh.set_norm(net.get_norm())
+    z1, z2 = rec[:, :3000].clone(), rec[:, :3000].clone()
+    net.apply(z1, n=3000)
+    fresh.apply(z2, n=3000)
+    assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy())
+
+
 def test_concurrent_training_equals_sequential(hbl, pairs):
     """PReLU networks trained at the same time on streams of their own
     (train_concurrently) equal one-after-another training bitwise."""
