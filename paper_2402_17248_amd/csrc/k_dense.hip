@@ -437,40 +437,68 @@ __global__ __launch_bounds__(256 * WM) __attribute__((amdgpu_waves_per_eu(WM, WM
 // NK = Wp/32 K chunks, fixed at compile time: the loop is unrolled and every
 // ring slot is a constant.  Each accumulator takes its chunks in order, one
 // 16x16x32 product per chunk, as in k_dense_layer: the two kernels give the
-// same bits.
-constexpr int kBlkMinMT = 8, kBlkMaxMT = 15;
-template <int MT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dense_hidden_blk(LayerArgs a) {
+// same bits.  An item is one (M block, 256-particle tile).  PERSIST: a
+// workgroup per CU walks items id, id + G, ...; after an item's last
+// products it starts the next item's first three chunks, so that their
+// loads fly during this item's epilogue (the biases come through LDS, so
+// that the epilogue does not wait on the vector-memory counter behind
+// them).  Without PERSIST (MT 14 and 15, whose register budget does not hold
+// the next item's operands beside the epilogue) one item per workgroup.
+constexpr int kBlkMinMT = 8, kBlkMaxMT = 15, kBlkPersistMaxMT = 13;
+constexpr int kPersistGroups = 256;                  // one workgroup per compute unit (a multiple of the 8 XCDs)
+template <int MT, bool PERSIST>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_dense_hidden_blk(LayerArgs a,
+                                                                                                       int n_items) {
     constexpr int NK = 2 * MT, K = NK * kKc, ROWS = MT * 16, PROWS = kWaves * kNT * 16, A_BYTES = ROWS * 64;
     constexpr int A_PER_WAVE = (MT + kWaves - 1) / kWaves, PER_CHUNK = A_PER_WAVE + kNT, BR = kStages + 1;
     static_assert(MT <= kBlkMaxMT, "MT x 4 x 4 accumulators fit the 256 accumulator registers");
-    __shared__ __attribute__((aligned(1024))) char smem[kStages * A_BYTES];
-    int m, tile;
-    tile_of(blockIdx.x, a.mblocks, m, tile);
-    if (tile >= a.tiles) return;                        // whole workgroup: no barrier follows
+    static_assert(ROWS * 4 <= 1024, "an M block's biases fit one 1 KB LDS buffer");
+    __shared__ __attribute__((aligned(1024))) char smem[kStages * A_BYTES + 2048];
+    const int G = PERSIST ? (int)gridDim.x : n_items;   // item stride
+    int id = blockIdx.x, m = 0, tile = 0;
+    auto valid = [&](int i, int& mm, int& tt) {
+        if (i >= n_items) return false;
+        tile_of(i, a.mblocks, mm, tt);
+        return tt < a.tiles;
+    };
+    while (id < n_items && !valid(id, m, tile)) id += G;
+    if (id >= n_items) return;                          // whole workgroup: no barrier follows
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r = lane & 15;
     const int64_t R = (int64_t)a.tiles * PROWS;         // rows of this launch's X and Y
-    const int64_t wrow0 = (int64_t)tile * PROWS + wave * (kNT * 16);
-    const uint16_t* xl = a.x + (wrow0 + r) * 32 + 8 * g;
-    const uint16_t* wm0 = a.w + (int64_t)m * ROWS * 32;
     typedef __attribute__((address_space(3))) char lds_char;
     lds_char* sm = (lds_char*)smem;
+    lds_char* bias_lds = sm + kStages * A_BYTES;        // two 1 KB buffers, by item parity
     bf16x8 bq[BR][kNT];                                 // particle operands, chunk kc in slot kc % BR
     bf16x8 aq[2][MT];                                   // weight operands of chunks kc (even/odd)
     f32x4 acc[MT][kNT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int par = 0;
+    const uint16_t* xnext = nullptr;                    // the next chunk's particle rows (this lane)
+    const uint16_t* wnext = nullptr;                    // the next chunk's weight rows (M block)
+    // an item's biases into LDS (wave 0, before its chunk 0) and its chunk pointers
+    auto start = [&](int im, int itile, int ipar) {
+        if (wave == 0) {
+            const float* src = a.bias + im * ROWS + min(lane * 4, ROWS - 4);
+            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(bias_lds + ipar * 1024),
+                                             16, 0, 0);
+        }
+        wnext = a.w + (int64_t)im * ROWS * 32;
+        xnext = a.x + ((int64_t)itile * PROWS + wave * (kNT * 16) + r) * 32 + 8 * g;
+    };
+    // chunk kc of the started item: weights into LDS stage kc % kStages, this
+    // wave's particles into register slot kc % BR; chunks are issued in order
     auto issue = [&](int kc) {
         lds_char* A = sm + (kc % kStages) * A_BYTES;
 #pragma unroll
         for (int i = 0; i < A_PER_WAVE; ++i) {
             const int j = min(wave + i * kWaves, MT - 1);
-            dma_rows16(wm0 + ((int64_t)kc * K + j * 16) * 32, 32, j * 16, 0, A + j * 1024, lane);
+            dma_rows16(wnext + j * 16 * 32, 32, j * 16, 0, A + j * 1024, lane);
         }
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) bq[kc % BR][nt] = *(const bf16x8*)(xl + ((int64_t)kc * R + nt * 16) * 32);
+        for (int nt = 0; nt < kNT; ++nt) bq[kc % BR][nt] = *(const bf16x8*)(xnext + nt * 16 * 32);
+        wnext += (int64_t)K * 32;
+        xnext += R * 32;
+        asm volatile("" : "+s"(wnext));                 // one running pointer, not NK precomputed ones
+        asm volatile("" : "+v"(xnext));
     };
     auto read_a = [&](int kc) {
         const lds_char* A = sm + (kc % kStages) * A_BYTES;
@@ -487,51 +515,79 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             for (int nt = 0; nt < kNT; ++nt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[kc & 1][mt], bq[kc % BR][nt], acc[mt][nt], 0, 0, 0);
     };
+    start(m, tile, 0);
 #pragma unroll
-    for (int kc = 0; kc < kStages - 1; ++kc)
-        if (kc < NK) issue(kc);
+    for (int kc = 0; kc < kStages - 1; ++kc) issue(kc);
+    const float s = *a.slope;
+    for (;;) {
 #pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        // chunk c readable: this wave's loads of it have landed (the loads of
-        // the chunks after it, up to c + kStages - 2, may be pending) and every
-        // wave's operand reads of chunk c - 1 are done, so its stage and its
-        // register slot take chunk c + kStages - 1
-        const int after = min(c + kStages - 2, NK - 1) - c;
-        if (after >= 2) wait_vm<2 * PER_CHUNK>();
-        else if (after == 1) wait_vm<PER_CHUNK>();
-        else wait_vm<0>();
-        __builtin_amdgcn_s_waitcnt(0xC07F);             // lgkmcnt(0) only
-        asm volatile("s_barrier" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
-        const bool more = c + kStages - 1 < NK;
-        if (more) issue(c + kStages - 1);
-        read_a(c);
-        if (c > 0) products(c - 1);
-        // the loads first, then each operand read of chunk c beside the kNT
-        // products of chunk c - 1 that use the register it replaces
-        if (more) __builtin_amdgcn_sched_group_barrier(0x010, PER_CHUNK, 0);
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            // chunk c readable: this wave's loads of it have landed (the loads
+            // of the chunks after it, up to c + kStages - 2, may be pending)
+            // and every wave's operand reads of chunk c - 1 are done, so its
+            // stage and its register slot take chunk c + kStages - 1
+            const int after = min(c + kStages - 2, NK - 1) - c;
+            if (after >= 2) wait_vm<2 * PER_CHUNK>();
+            else if (after == 1) wait_vm<PER_CHUNK>();
+            else wait_vm<0>();
+            __builtin_amdgcn_s_waitcnt(0xC07F);         // lgkmcnt(0) only
+            asm volatile("s_barrier" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            const bool more = c + kStages - 1 < NK;
+            if (more) issue(c + kStages - 1);
+            read_a(c);
+            if (c > 0) products(c - 1);
+            // the loads first, then each operand read of chunk c beside the
+            // kNT products of chunk c - 1 that use the register it replaces
+            if (more) __builtin_amdgcn_sched_group_barrier(0x010, PER_CHUNK, 0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                if (c > 0) __builtin_amdgcn_sched_group_barrier(0x008, kNT, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        products(NK - 1);
+        int nid = id + G, nm = m, ntile = tile;
+        while (nid < n_items && !valid(nid, nm, ntile)) nid += G;
+        const bool last = nid >= n_items;
+        if (PERSIST) {
+            // every wave is done with this item's LDS stages; the next item's
+            // first chunks (after the last item: this item's again, never read,
+            // so that the loads and the counts below do not depend on a branch)
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            asm volatile("s_barrier" ::: "memory");
+            if (last) { nm = m; ntile = tile; }
+            start(nm, ntile, par ^ 1);
+#pragma unroll
+            for (int kc = 0; kc < kStages - 1; ++kc) issue(kc);
+        } else {
+            wait_vm<0>();                               // the biases
+            asm volatile("s_barrier" ::: "memory");
+        }
+        const int64_t row0 = (int64_t)tile * PROWS + wave * (kNT * 16) + r;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            if (c > 0) __builtin_amdgcn_sched_group_barrier(0x008, kNT, 0);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    products(NK - 1);
-    const float s = *a.slope;
+            const int o = m * ROWS + mt * 16 + 4 * g;
+            const f32x4 bb = *(const __attribute__((address_space(3))) f32x4*)(bias_lds + par * 1024 + (mt * 16 + 4 * g) * 4);
+            uint16_t* yo = a.y + ((int64_t)(o >> 5) * R + row0) * 32 + (o & 31);
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const int o = m * ROWS + mt * 16 + 4 * g;
-        const f32x4 bb = *(const f32x4*)(a.bias + o);
-        uint16_t* yo = a.y + ((int64_t)(o >> 5) * R + wrow0 + r) * 32 + (o & 31);
-#pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) {
-            const f32x4 v = acc[mt][nt];
-            const u32x2 st = {pack2(prelu(v[0] + bb[0], s), prelu(v[1] + bb[1], s)),
-                              pack2(prelu(v[2] + bb[2], s), prelu(v[3] + bb[3], s))};
-            *(u32x2*)(yo + nt * 16 * 32) = st;
+            for (int nt = 0; nt < kNT; ++nt) {
+                const f32x4 v = acc[mt][nt];
+                const u32x2 st = {pack2(prelu(v[0] + bb[0], s), prelu(v[1] + bb[1], s)),
+                                  pack2(prelu(v[2] + bb[2], s), prelu(v[3] + bb[3], s))};
+                *(u32x2*)(yo + nt * 16 * 32) = st;
+            }
+            __builtin_amdgcn_sched_barrier(0);          // one row of tiles at a time: registers
         }
+        if (!PERSIST || last) break;
+        id = nid; m = nm; tile = ntile; par ^= 1;
     }
+    wait_vm<0>();                                       // no load in flight when the wave ends
 }
 
 // ------------------------------------------------------------ training
@@ -835,7 +891,10 @@ int hidden_mt(int wp) {
 
 template <int MT>
 hipError_t launch_hidden_blk(const LayerArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_hidden_blk<MT>, dim3(layer_grid(a)), dim3(kBlock), 0, s, a);
+    const int items = layer_grid(a);
+    constexpr bool P = MT <= kBlkPersistMaxMT;
+    const int grid = P && items > kPersistGroups ? kPersistGroups : items;
+    hipLaunchKernelGGL((k_dense_hidden_blk<MT, P>), dim3(grid), dim3(kBlock), 0, s, a, items);
     return hipGetLastError();
 }
 constexpr LayerLauncher kHiddenBlk[kBlkMaxMT - kBlkMinMT + 1] = {
