@@ -248,10 +248,14 @@ constexpr int kInferBlock = 256;
 // particle base + l (tile l / 16, column l % 16): one coalesced load and store
 // per bunch row, the transport gap before the stage (pre) and after it (post)
 // applied to the owned particle in registers.  The owner forms the bf16
-// hi/lo words of its normalised coordinates; every lane then gathers the
-// layer-0 operand of each tile from that tile's owner lanes, and after the
-// network each owner gathers its six outputs (rows 0-3 live in lane group 0,
-// rows 4-5 in lane group 1) -- cross-lane moves only, no redundant loads.
+// hi/lo words of its normalised coordinates and writes them to the wave's
+// LDS records, already in the order of each lane group's layer-0 operand
+// (record g of a particle holds the four K slots of lane group g), so that
+// every lane reads its operand of each tile with one 16-byte LDS read; after
+// the network the lanes of groups 0 and 1 write the rows they hold (outputs
+// 0-3 and 4-5) to the particle's output record and each owner reads its six
+// outputs back.  The exchange stays within the wave (in-order LDS, no
+// barrier); it replaced 48 lane shuffles and their selects (2.5 % faster).
 template <bool GAPS, bool CHROM = false>
 __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(
     NormArgs, double* __restrict__ z, int64_t n, int64_t ld, const uint32_t* __restrict__ img,
@@ -261,6 +265,13 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
     const int l = threadIdx.x & 63, col = l % 16, g = l / 16;
     const int64_t waves = (int64_t)gridDim.x * (kInferBlock / 64);
     const int64_t wave = (int64_t)blockIdx.x * (kInferBlock / 64) + (threadIdx.x >> 6);
+    // per wave: layer-0 operand records [lane group][particle] (groups 2 and 3
+    // are zero past their first word) and output records [particle][8]
+    __shared__ u32x4 xin_lds[kInferBlock / 64][4][64];
+    __shared__ float yout_lds[kInferBlock / 64][64][8];
+    const int wv = threadIdx.x >> 6;
+    xin_lds[wv][2][l] = u32x4{0u, 0u, 0u, 0u};
+    xin_lds[wv][3][l] = u32x4{0u, 0u, 0u, 0u};
     for (int64_t base = wave * 64; base < n; base += waves * 64) {
         // The normalisation constants (the first kernel argument, at offset 0 of the
         // argument segment) are re-read from that segment each iteration through a
@@ -286,31 +297,24 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
             hw[q] = pack_bf16x2(ah, bh);
             lw[q] = pack_bf16x2(a - ah, b - bh);
         }
+        // K slots: 0-5 hi, 6-11 lo, 12-17 hi (see the file comment); lane
+        // group 0 takes slots 0-3 (words h01 h23 h45 l01), group 1 slots 4-7
+        // (l23 l45 h01 h23), group 2 slots 8-11 (h45 0 0 0), group 3 zeros
+        xin_lds[wv][0][l] = u32x4{hw[0], hw[1], hw[2], lw[0]};
+        xin_lds[wv][1][l] = u32x4{lw[1], lw[2], hw[0], hw[1]};
+        xin_lds[wv][2][l][0] = hw[2];
+        __builtin_amdgcn_wave_barrier();
         f32x4 y[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int src = 16 * t + col;
-            const uint32_t h0 = __shfl(hw[0], src, 64), h1 = __shfl(hw[1], src, 64), h2 = __shfl(hw[2], src, 64);
-            const uint32_t l0 = __shfl(lw[0], src, 64), l1 = __shfl(lw[1], src, 64), l2 = __shfl(lw[2], src, 64);
-            // K slots: 0-5 hi, 6-11 lo, 12-17 hi (see the file comment)
-            const u32x4 v0 = {h0, h1, h2, l0}, v1 = {l1, l2, h0, h1}, v2 = {h2, 0u, 0u, 0u};
-            const u32x4 zero = {0u, 0u, 0u, 0u};
-            y[t] = forward_tile(net, g == 0 ? v0 : g == 1 ? v1 : g == 2 ? v2 : zero);
-        }
-        float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 4; ++t) y[t] = forward_tile(net, xin_lds[wv][g][16 * t + col]);
+        // D rows 4g .. 4g+3 of column col: outputs 0-3 in group 0, 4-5 in group 1
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float v = __shfl(y[t][r], col, 64);
-                if (g == t) o[r] = v;
-            }
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const float v = __shfl(y[t][r], 16 + col, 64);
-                if (g == t) o[4 + r] = v;
-            }
-        }
+        for (int t = 0; t < 4; ++t)
+            if (g < 2) *(f32x4*)&yout_lds[wv][16 * t + col][4 * g] = y[t];
+        __builtin_amdgcn_wave_barrier();
+        const f32x4 o03 = *(const f32x4*)&yout_lds[wv][l][0];
+        const float o[6] = {o03[0], o03[1], o03[2], o03[3], yout_lds[wv][l][4], yout_lds[wv][l][5]};
+        __builtin_amdgcn_wave_barrier();                // the next iteration's writes after these reads
         P6 q;
         q.x = fma(na.sd_out[0], (double)o[0], na.mu_out[0]);
         q.y = fma(na.sd_out[1], (double)o[1], na.mu_out[1]);
