@@ -500,13 +500,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         asm volatile("" : "+s"(wnext));                 // one running pointer, not NK precomputed ones
         asm volatile("" : "+v"(xnext));
     };
+    // LDS offset of this lane's operand piece in row tile mt: swz(16 mt + r) =
+    // swz(r) ^ (2 mt & 3), so two lane offsets serve every tile (the tile and
+    // stage parts are immediates of the LDS reads)
+    const int a_off_even = r * 64 + ((g ^ swz(r)) * 16), a_off_odd = r * 64 + ((g ^ swz(r) ^ 2) * 16);
     auto read_a = [&](int kc) {
         const lds_char* A = sm + (kc % kStages) * A_BYTES;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int ar = mt * 16 + r;
-            aq[kc & 1][mt] = *(const __attribute__((address_space(3))) bf16x8*)(A + ar * 64 + ((g ^ swz(ar)) * 16));
-        }
+        for (int mt = 0; mt < MT; ++mt)
+            aq[kc & 1][mt] = *(const __attribute__((address_space(3))) bf16x8*)(A + mt * 1024 + ((mt & 1) ? a_off_odd
+                                                                                                    : a_off_even));
     };
     auto products = [&](int kc) {
 #pragma unroll
