@@ -283,8 +283,9 @@ __global__ __launch_bounds__(kInferBlock) __attribute__((amdgpu_waves_per_eu(2, 
         const int64_t i = base + l;
         const bool live = i < n;
         P6 p;
-        if (live) load6(z, ld, i, p);
-        else p = P6{na.mu_in[0], na.mu_in[1], na.mu_in[2], na.mu_in[3], na.mu_in[4], na.mu_in[5]};
+        // a lane past the end computes on the last particle (its own column of
+        // every product, never stored): the loads need no branch
+        load6(z, ld, live ? i : n - 1, p);
         if constexpr (GAPS && CHROM) apply_elements<true>(p, pre);
         else if constexpr (GAPS) apply_elements_asm(p, pre);
         const double pv[6] = {p.x, p.y, p.t, p.px, p.py, p.pt};
