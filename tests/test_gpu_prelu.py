@@ -157,11 +157,13 @@ def test_full_size_sampled(hbl, orc, width, hidden):
     assert mx < 5e-3 and med < 1e-7 and frac < 0.01
 
 
-@pytest.mark.parametrize("width,hidden", [(8, 1), (72, 2), (136, 3), (250, 2), (500, 2), (520, 7), (1024, 2)])
+@pytest.mark.parametrize("width,hidden", [(8, 1), (72, 2), (136, 3), (250, 2), (500, 2), (520, 7), (600, 2),
+                                          (750, 2), (800, 2), (880, 2), (1024, 2)])
 def test_forward_parity_other_widths(hbl, orc, width, hidden):
     """Widths that pick every kind of M block (4 to 12 MFMA tiles, one to
-    eight blocks per layer, row-major), the narrowest K-blocked width
-    (W' = 512), the deepest and the widest network allowed."""
+    eight blocks per layer, row-major), every K-blocked width class (W' =
+    512 .. 896: 8 to 14 row tiles per M block, persistent up to 13), the
+    deepest and the widest network allowed."""
     sh = orc.shape(width=width, hidden=hidden)
     m = 700
     x, norm = bunch(orc, m, 24)
