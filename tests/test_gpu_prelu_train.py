@@ -150,9 +150,11 @@ def test_training_matches_oracle_loop(hbl, orc, pairs):
     assert np.linalg.norm(pg - p) < 0.03 * moved
 
 
-def test_save_load_roundtrip(hbl, orc, pairs, tmp_path):
+@pytest.mark.parametrize("width", [72, 520])
+def test_save_load_roundtrip(hbl, orc, pairs, tmp_path, width):
+    """Row-major (W' = 128) and K-blocked (W' = 576) inference images are rebuilt on load."""
     n, rec, out, xin, xout = pairs
-    net = hbl.PreluNet(72, 2, 4)
+    net = hbl.PreluNet(width, 2, 4)
     net.train(rec, out, n, batch=500, epochs=1, lr=1e-3, shuffle_seed=2)
     wl = W.c3_stage(n=8)
     entry = hbl.Ref.from_energy(wl.E_MeV)
@@ -160,7 +162,7 @@ def test_save_load_roundtrip(hbl, orc, pairs, tmp_path):
     path = str(tmp_path / "net.bin")
     net.save(path)
     back = hbl.PreluNet.load(path)
-    assert (back.width, back.hidden) == (72, 2)
+    assert (back.width, back.hidden) == (width, 2)
     assert np.array_equal(back.get_params(), net.get_params())
     assert back.get_norm() == net.get_norm()
     z1, z2 = rec[:, :1000].clone(), rec[:, :1000].clone()
