@@ -352,7 +352,7 @@ hbl_status hbl_surrogate_load(const char* path, hbl_surrogate** out);
  * activation rounded to bf16; output FP32, de-normalised in FP64.
  * Device memory held by a network: its parameters, their bf16 image (for
  * 512 <= W' <= 960 with a second, K-blocked copy of the W x W layers) and two
- * activation buffers of 65536 x W' bf16 (W' = W rounded up to 64; 2 x 126 MB
+ * activation buffers of chunk x W' bf16 (W' = W rounded up to 64; 2 x 126 MB
  * at W = 900), allocated at creation.  Calls that use one network must be
  * ordered (one stream, or synchronised): they share those buffers. */
 typedef struct hbl_prelu_net hbl_prelu_net;
@@ -367,7 +367,8 @@ hbl_status hbl_prelu_num_params(const hbl_prelu_net* m, int64_t* n);
 /* SYNC.  Copy the FP32 parameters to / from host memory (n floats, finite). */
 hbl_status hbl_prelu_get_params(const hbl_prelu_net* m, float* host, int64_t n);
 hbl_status hbl_prelu_set_params(hbl_prelu_net* m, const float* host, int64_t n);
-/* SYNC.  Particles per inference chunk (default 65536; a multiple of 256 in
+/* SYNC.  Particles per inference chunk (default 98304 at 512 <= W' <= 832,
+ * 65536 otherwise; a multiple of 256 in
  * [256, 2^22]): the two activation buffers hold chunk x W' bf16 each.
  * Smaller chunks keep the activations in the last-level cache; larger ones
  * give each layer launch more workgroups.  HBL_ENOMEM leaves the old ones. */
@@ -378,7 +379,7 @@ hbl_status hbl_prelu_get_norm(const hbl_prelu_net* m, double norm24[24]);
 /* Declare the stage the network replaces (as hbl_surrogate_set_stage). */
 hbl_status hbl_prelu_set_stage(hbl_prelu_net* m, const hbl_element* stage, const hbl_ref* at_entry);
 /* ASYNC.  Inference in place on n particles of the DEVICE bunch z (§4.3),
- * in chunks of 65536 particles; advances ref like the declared stage. */
+ * in chunks (hbl_prelu_set_chunk); advances ref like the declared stage. */
 hbl_status hbl_prelu_apply(double* z, int64_t n, int64_t ld, const hbl_prelu_net* m, hbl_ref* ref,
                            hbl_stream stream);
 /* ASYNC.  pre lattice, the network, post lattice in the same launches (pre

@@ -89,6 +89,7 @@ def test_forward_ragged_and_chunked(hbl, orc, width, m):
     x, norm = bunch(orc, m + 5, 22)
     p = perturbed(orc, sh, 8)
     net = hbl.PreluNet(width, 2, 0)
+    net.set_chunk(65536)                               # m = 65536 + 300 spans two chunks
     net.set_params(p)
     net.set_norm(norm)
     z = to_dev(x)
