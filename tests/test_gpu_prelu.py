@@ -181,18 +181,21 @@ def test_forward_parity_other_widths(hbl, orc, width, hidden):
     assert mx < 5e-3 and med < 1e-7 and frac < 0.01
 
 
-def test_chunk_size_does_not_change_results(hbl, orc):
-    """Chunking only splits the particles: any chunk gives the same bits."""
+@pytest.mark.parametrize("width", [136, 600])
+def test_chunk_size_does_not_change_results(hbl, orc, width):
+    """Chunking only splits the particles: any chunk gives the same bits, on
+    row-major activations and on K-blocked ones (whose block stride is the
+    chunk's row count)."""
     m = 5000
     x, norm = bunch(orc, m, 25)
-    net = hbl.PreluNet(136, 3, 7)
+    net = hbl.PreluNet(width, 3, 7)
     net.set_norm(norm)
     outs = []
-    for ch in (65536, 256, 1024):
+    for ch in (65536, 256, 1024, 98304):
         net.set_chunk(ch)
         z = to_dev(x)
         net.apply(z, n=m)
         outs.append(to_host(z, m))
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
     with pytest.raises(hbl.HblError):
         net.set_chunk(1000)
